@@ -1,0 +1,225 @@
+/*
+ * rr.h -- C ABI of the MI355X randomized resolvent library (librr.so).
+ *
+ * Randomized resolvent analysis (Ribeiro, Yeh & Taira, arXiv:1902.01458):
+ * for a real linear operator L (eq. 1) and a frequency omega, the leading
+ * singular values sigma_j (gains) and singular vectors (forcing modes v_j,
+ * response modes u_j) of the resolvent H(omega) = (i omega I - L)^-1
+ * (eq. 4-5) are found from a thin random sketch (Algorithm 1).
+ *
+ * Sign convention: the paper writes the resolvent as (-i omega I - L)^-1 for
+ * an e^{-i omega t} transform; this library uses M(omega) = i omega I - L.
+ * For real L and real omega the gains agree and the modes are conjugated.
+ * A complex omega = omega_r + i beta gives the discounted resolvent of the
+ * paper's Section 2.1.
+ *
+ * Call sequence (Algorithm 1):
+ *   rr_factor        one LU of M(omega) per shift, reused by every solve
+ *                    (Section 3.1: the factorisation is computed once and
+ *                    passed to the three linear solves)
+ *   rr_sketch_solve  steps 1-3 plus the power/subspace iteration of
+ *                    Section 2.2.1: Theta = diag(Phi) Omega (eq. 10),
+ *                    Y = M^-1 Theta, Q = orth(Y)
+ *   rr_adjoint_solve step 4: Z = M^-H Q, so that B = Q^H H = Z^H
+ *   rr_gains         step 5 (SVD of B), eq. 8 (Halko response modes Q Ut) and
+ *                    steps 6-9 (eq. 9: H v_j = sigma_j u_j, the paper's
+ *                    recovery of sigma_j and u_j)
+ *   rr_grad          d sigma_1 / d(U, nu, omega) by first-order perturbation
+ *                    of eq. 5 (not in the paper; see rr_grad below)
+ *
+ * Conventions for every entry point
+ *   - Complex arrays are interleaved (re, im) doubles (torch.complex128).
+ *   - Blocks of vectors are (n_omega, k, n): column j of shift w starts at
+ *     element (w*k + j)*n, each column contiguous.
+ *   - Pointers documented as "device" must be device memory of the current
+ *     HIP device; "host" pointers are read before the call returns.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). All work
+ *     is ordered on it; entry points return before the GPU work completes,
+ *     except rr_factors_create (host allocations) and rr_check (syncs).
+ *   - The caller owns all input and output buffers; the library owns the
+ *     rr_factors handle and everything it allocated for it.
+ *   - Errors visible on the host (bad sizes, NULL pointers, allocation
+ *     failure) are returned before anything is launched. Errors found on the
+ *     device (zero pivot, non-finite values, Cholesky breakdown, refinement
+ *     not converged) are latched in the handle and returned by rr_check.
+ *     After an error the contents of the outputs are unspecified.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - No call allocates device memory except rr_factor (which sizes every
+ *     workspace for k <= k_max) and rr_burgers_coeffs (none); so the
+ *     sequence sketch_solve / adjoint_solve / gains / grad can be captured
+ *     into a HIP graph.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RR_OK = 0,
+  RR_ERR_INVALID = 1,        /* bad argument (size, pointer, option)          */
+  RR_ERR_SINGULAR = 2,       /* zero or non-finite pivot in the band LU       */
+  RR_ERR_NOT_CONVERGED = 3,  /* mixed-precision refinement missed tolerance   */
+  RR_ERR_BREAKDOWN = 4,      /* Gram matrix not positive definite (CholQR)    */
+  RR_ERR_NONFINITE = 5,      /* NaN/Inf in inputs or results                  */
+  RR_ERR_NOMEM = 6,          /* device allocation failed                      */
+  RR_ERR_HIP = 7,            /* HIP runtime error (sticky for the handle)     */
+  RR_ERR_TIMEOUT = 8         /* a dataflow wait exceeded its bound (bug)      */
+} rr_status;
+
+typedef enum {
+  RR_FP64 = 0,   /* complex FP64 factor and solves (FP64 MFMA)                */
+  RR_MIXED = 1   /* complex FP32 factor and solves (FP32 MFMA, FP32
+                    accumulation) + iterative refinement whose residual
+                    M x - b is computed in FP64 from the stencil              */
+} rr_precision;
+
+typedef enum {
+  RR_RESP_AV = 0,   /* u_j = M^-1 v_j / ||M^-1 v_j||  (eq. 9, Alg. 1 steps 6-9) */
+  RR_RESP_QU = 1,   /* u_j = Q Ut_j                    (eq. 8, Halko et al.)    */
+  RR_RESP_NONE = 2  /* gains and forcing modes only                             */
+} rr_response;
+
+/* The operator L: 12 real stencil coefficients per interior node of an
+ * nx x ny grid.  Node p = j + ny*i (y fastest); unknown 2p is the u-component
+ * and 2p+1 the v-component at node p, so the half-bandwidth is 2*ny.
+ *   coef[12*p + 0..5]  u-row: C (u_p), E (u at i+1), W (i-1), N (j+1), S (j-1),
+ *                      Cpl (v_p)
+ *   coef[12*p + 6..11] v-row: C (v_p), E, W, N, S, Cpl (u_p)
+ * Neighbours outside the grid contribute nothing (homogeneous Dirichlet).
+ * Any operator of this shape is accepted (the tests feed normal operators
+ * with closed-form gains through it); rr_burgers_coeffs fills it for the
+ * linearised viscous Burgers operator. */
+typedef struct {
+  int32_t nx, ny;
+  const double* coef;  /* device, nx*ny*12                                       */
+  const double* phi;   /* device, nx*ny sketch row weights (eq. 10), or NULL
+                          for the unweighted Gaussian test matrix of Alg. 1 l.1  */
+  /* Optional Burgers description, needed only by rr_grad:                       */
+  const double* U;     /* device, (nx+2)*(ny+2) base flow incl. the boundary
+                          ring, index i*(ny+2)+j; NULL if rr_grad is not used    */
+  double x0, x1, y0, y1, nu;  /* domain and viscosity (grid spacing
+                          h = (x1-x0)/(nx+1), (y1-y0)/(ny+1))                     */
+} rr_problem;
+
+/* Tuning knobs; pass NULL to rr_factor for defaults (or the autotuner's pick). */
+typedef struct {
+  int32_t tile;          /* band tile edge T: 32 or 64 (default 64)             */
+  int32_t grid;          /* persistent workgroups per launch; 0 = 2 per CU      */
+  int32_t refine_iters;  /* mixed only: fixed correction count per solve
+                            (default 3); convergence is still checked           */
+  double  refine_tol;    /* mixed only: per-column ||d_j|| <= tol*||x_j||
+                            (default 1e-10)                                     */
+} rr_tuning;
+
+typedef struct rr_factors rr_factors;
+
+/* Fill coef (and phi) for the 2-D linearised viscous Burgers operator about
+ * the base flow (U(x,y), V = 0) with second-order central differences:
+ *   u-row: nu Lap u - U u_x - U_x u - U_y v;   v-row: nu Lap v - U v_x
+ * U_x, U_y are central differences of the nodal U (ring values included);
+ * phi = sqrt(U_x^2 + U_y^2) + 0.1, the base-flow gradient weighting of the
+ * physics-informed test matrix (eq. 10).  U: device (nx+2)*(ny+2); coef_out:
+ * device nx*ny*12; phi_out: device nx*ny or NULL. */
+rr_status rr_burgers_coeffs(int32_t nx, int32_t ny, const double* U, double x0, double x1,
+                            double y0, double y1, double nu, double* coef_out,
+                            double* phi_out, void* stream);
+
+/* Apply the shifted operator: Y = M(omega_w) X for every shift w (FP64, from
+ * the stencil; used for residuals and tests).  X, Y: device (n_omega, k, n)
+ * complex.  omega_re/omega_im: host, n_omega each (omega_im may be NULL).
+ * adjoint != 0 applies M^H instead. */
+rr_status rr_apply(const rr_problem* p, const double* omega_re, const double* omega_im,
+                   int32_t n_omega, int32_t k, int32_t adjoint, const double* X, double* Y,
+                   void* stream);
+
+/* Factor M(omega_w) = L_w U_w (no pivoting, band kl = ku = 2*ny) for each of
+ * the n_omega shifts; the factors live in the returned handle, which also
+ * takes private copies of coef, phi and U.  k_max bounds the sketch width of
+ * later calls (workspaces are sized for it).  omega_re / omega_im: host arrays
+ * of n_omega doubles (omega_im may be NULL: real shifts).  On success *out is
+ * a new handle; the factorisation itself is enqueued on `stream` and its
+ * device-side status is reported by rr_check. */
+rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* omega_im,
+                    int32_t n_omega, int32_t k_max, rr_precision prec,
+                    const rr_tuning* tune, void* stream, rr_factors** out);
+
+/* Re-run the factorisation in place for the same shifts (e.g. inside a graph
+ * or to time it).  Same semantics as the factorisation part of rr_factor. */
+rr_status rr_refactor(rr_factors* f, void* stream);
+
+/* Steps 1-3 of Algorithm 1 with q rounds of subspace iteration (Section
+ * 2.2.1): Theta[r, j] = phi[r/2] * w(r, j) with w a standard complex normal
+ * drawn by Box-Muller from Philox4x32-10 at counter (r, j, 0, 0) under key
+ * (seed & 0xffffffff, seed >> 32); one Theta shared by every shift.  Then
+ * Y = M^-1 Theta, Q = orth(Y); q times: Q = orth(M^-1 orth(M^-H Q)).
+ * orth() is Cholesky QR applied twice (Gram and Cholesky in FP64), whose R
+ * has a real positive diagonal.  Q: device (n_omega, k, n) complex output. */
+rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power_iters,
+                          double* Q, void* stream);
+
+/* Step 4: Z = M^-H Q for every shift (B = Z^H).  Q, Z: device (n_omega, k, n). */
+rr_status rr_adjoint_solve(rr_factors* f, int32_t k, const double* Q, double* Z, void* stream);
+
+/* Plain forward solve X = M^-1 Bm for every shift (with refinement in the
+ * mixed path).  Bm, X: device (n_omega, k, n).  X may not alias Bm. */
+rr_status rr_solve(rr_factors* f, int32_t k, const double* Bm, double* X, void* stream);
+
+/* Steps 5-9: SVD of B = Z^H (via Z = Qz R, SVD of the k x k R^H = Ut S W^H)
+ * gives sigma_B (descending) and the forcing modes V = Qz W.  Then
+ *   RR_RESP_AV: Us = M^-1 V, sigma_AV_j = ||Us_j||, Uresp_j = Us_j/sigma_AV_j
+ *   RR_RESP_QU: Uresp = Q Ut (sigma_AV untouched)
+ * sigma_B, sigma_AV: device n_omega*k doubles (sigma_AV may be NULL unless
+ * mode is RR_RESP_AV); V, Uresp: device (n_omega, k, n) complex (Uresp may be
+ * NULL for RR_RESP_NONE).  Q is needed only for RR_RESP_QU. */
+rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z,
+                   rr_response mode, double* sigma_B, double* sigma_AV, double* V,
+                   double* Uresp, void* stream);
+
+/* Gradient of the leading gain (not part of the paper's method): for a
+ * simple sigma with H v = sigma u and u^H H = sigma v^H, a perturbation gives
+ *   d sigma / dp     = sigma^2 Re(v^H (dL/dp) u)   for p = U at a node, nu
+ *   d sigma / domega = sigma^2 Im(v^H u)
+ * evaluated as a stencil reduction.  Needs the Burgers description in the
+ * problem (U != NULL).  sigma1: device n_omega; u1, v1: device n_omega vectors
+ * of n complex (response, forcing), at stride `vec_stride` complex elements
+ * between shifts (k*n for the first column of a (n_omega, k, n) block);
+ * dU: device n_omega*nx*ny; dnu, domega: device n_omega each. */
+rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const double* v1,
+                  int64_t vec_stride, double* dU, double* dnu, double* domega, void* stream);
+
+/* Synchronise `stream` and return (then clear) the first device-side error
+ * latched in the handle since the last check; RR_OK if none. */
+rr_status rr_check(rr_factors* f, void* stream);
+
+/* Number of correction steps the last mixed-precision solves needed at most
+ * (0 for FP64), read after rr_check. */
+int32_t rr_refine_count(rr_factors* f);
+
+/* Device bytes held by the handle. */
+size_t rr_bytes(const rr_factors* f);
+
+/* Free a handle (NULL-safe). Synchronises the device first. */
+void rr_factors_free(rr_factors* f);
+
+/* Message for the last error returned on this thread (never NULL). */
+const char* rr_last_error(void);
+
+/* Test hooks for the device random-number generator.
+ * rr_philox_raw: out_dev[4*i .. 4*i+3] = Philox4x32-10 output words of counter
+ * (i, c1, c2, 0) under key (k0, k1), for i < count (device, 4*count words).
+ * rr_sketch: the test matrix of rr_sketch_solve, Theta (k, n) complex
+ * (device), row weights p->phi (NULL = unweighted); p->coef is not read. */
+rr_status rr_philox_raw(uint32_t* out_dev, int64_t count, uint32_t c1, uint32_t c2, uint32_t k0,
+                        uint32_t k1, void* stream);
+rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, double* theta, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RR_H */

@@ -1,0 +1,15 @@
+"""Randomized resolvent analysis on the MI355X (gfx950).
+
+The hot path of Ribeiro, Yeh & Taira, "Randomized resolvent analysis"
+(arXiv:1902.01458), Algorithm 1: a physics-weighted Gaussian sketch, one band
+LU of i*omega*I - L per frequency, forward and adjoint multi-RHS solves,
+Cholesky-QR orthonormalisation, the reduced SVD and the recovery of gains and
+modes through eq. (9); plus mixed-precision refinement, batched frequency
+sweeps and the gradient of the leading gain.  All numerical work runs in the
+HIP kernels of librr.so; this package only marshals arguments.
+"""
+from .api import (BurgersProblem, Factors, factor, philox_raw, resolvent, sketch)  # noqa: F401
+from ._lib import RRError, lib  # noqa: F401
+
+__all__ = ["BurgersProblem", "Factors", "factor", "resolvent", "sketch", "philox_raw", "RRError",
+           "lib"]

@@ -1,0 +1,246 @@
+"""Python front end over the C ABI: device buffers are torch tensors, the
+stream is torch's current stream, every step runs in librr.so's kernels.
+
+    prob = BurgersProblem.from_workload(w)               # U, coefficients, Phi on the GPU
+    f = factor(prob, omegas, precision="mixed", k_max=20) # one LU per shift (Section 3.1)
+    Q = f.sketch_solve(k, seed, q)                        # Alg. 1 steps 1-3 (+ Section 2.2.1)
+    Z = f.adjoint_solve(Q)                                # step 4
+    out = f.gains(Q, Z, "av")                             # steps 5-9 (eq. 8, eq. 9)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+PRECISIONS = {"fp64": _lib.RR_FP64, "mixed": _lib.RR_MIXED}
+RESPONSES = {"av": _lib.RR_RESP_AV, "qu": _lib.RR_RESP_QU, "none": _lib.RR_RESP_NONE}
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class BurgersProblem:
+    """The operator of eq. (1) as the library consumes it (all on the GPU)."""
+    nx: int
+    ny: int
+    coef: torch.Tensor                 # (nx*ny*12,) float64
+    phi: Optional[torch.Tensor]        # (nx*ny,) float64 or None
+    U: Optional[torch.Tensor] = None   # ((nx+2)*(ny+2),) float64
+    domain: tuple = (0.0, 1.0, 0.0, 1.0)
+    nu: float = 0.0
+
+    @property
+    def n(self) -> int:
+        return 2 * self.nx * self.ny
+
+    @classmethod
+    def from_base_flow(cls, U: np.ndarray, nx: int, ny: int, domain, nu: float,
+                       weighted: bool = True, device="cuda") -> "BurgersProblem":
+        """Coefficients and Phi computed on the GPU (rr_burgers_coeffs)."""
+        Ud = torch.as_tensor(np.ascontiguousarray(U, dtype=np.float64).reshape(-1), device=device)
+        coef = torch.empty(nx * ny * 12, dtype=torch.float64, device=device)
+        phi = torch.empty(nx * ny, dtype=torch.float64, device=device) if weighted else None
+        check(lib().rr_burgers_coeffs(nx, ny, _ptr(Ud), *map(float, domain), float(nu),
+                                      _ptr(coef), _ptr(phi), ctypes.c_void_p(_stream())))
+        return cls(nx, ny, coef, phi, Ud, tuple(map(float, domain)), float(nu))
+
+    @classmethod
+    def from_workload(cls, w, weighted: bool = True, device="cuda") -> "BurgersProblem":
+        import workloads
+        return cls.from_base_flow(workloads.base_flow(w), w.nx, w.ny, w.domain, w.nu,
+                                  weighted=weighted, device=device)
+
+    @classmethod
+    def from_coefficients(cls, coef: np.ndarray, phi=None, device="cuda") -> "BurgersProblem":
+        """Any operator in the 12-coefficient stencil format, shape (nx, ny, 12)."""
+        nx, ny, _ = coef.shape
+        c = torch.as_tensor(np.ascontiguousarray(coef, dtype=np.float64).reshape(-1), device=device)
+        p = None if phi is None else torch.as_tensor(
+            np.ascontiguousarray(phi, dtype=np.float64).reshape(-1), device=device)
+        return cls(nx, ny, c, p)
+
+    def c_struct(self) -> _lib.Problem:
+        x0, x1, y0, y1 = self.domain
+        return _lib.Problem(self.nx, self.ny, self.coef.data_ptr(),
+                            self.phi.data_ptr() if self.phi is not None else None,
+                            self.U.data_ptr() if self.U is not None else None,
+                            x0, x1, y0, y1, self.nu)
+
+    def apply(self, omegas: Sequence[complex], X: torch.Tensor, adjoint: bool = False):
+        """Y = M(omega) X (or M^H X) for X of shape (n_omega, k, n) complex128."""
+        om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
+        n_om, k, n = X.shape
+        if n != self.n or n_om != om.size:
+            raise ValueError("shape mismatch")
+        Y = torch.empty_like(X)
+        re = np.ascontiguousarray(om.real)
+        im = np.ascontiguousarray(om.imag)
+        ps = self.c_struct()
+        check(lib().rr_apply(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
+                             im.ctypes.data_as(ctypes.c_void_p), n_om, k, int(adjoint),
+                             _ptr(X), _ptr(Y), ctypes.c_void_p(_stream())))
+        return Y
+
+
+class Factors:
+    """One band LU per shift (M(omega) = i omega I - L), owned by the library."""
+
+    def __init__(self, prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32,
+                 tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
+                 stream=None):
+        om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
+        self.prob = prob
+        self.omegas = om
+        self.n_omega = om.size
+        self.n = prob.n
+        self.k_max = k_max
+        self.precision = precision
+        self._h = ctypes.c_void_p()
+        re = np.ascontiguousarray(om.real)
+        im = np.ascontiguousarray(om.imag)
+        tune = _lib.Tuning(tile, grid, refine_iters, refine_tol)
+        ps = prob.c_struct()
+        check(lib().rr_factor(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
+                              im.ctypes.data_as(ctypes.c_void_p), self.n_omega, k_max,
+                              PRECISIONS[precision], ctypes.byref(tune),
+                              ctypes.c_void_p(_stream(stream)), ctypes.byref(self._h)))
+
+    # -- lifetime ----------------------------------------------------------
+    def free(self):
+        if self._h:
+            lib().rr_factors_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("factors were freed")
+        return self._h
+
+    def nbytes(self) -> int:
+        return int(lib().rr_bytes(self.handle))
+
+    def check(self, stream=None):
+        """Synchronise and raise on any device-side error latched so far."""
+        check(lib().rr_check(self.handle, ctypes.c_void_p(_stream(stream))))
+
+    def refine_count(self) -> int:
+        return int(lib().rr_refine_count(self.handle))
+
+    def refactor(self, stream=None):
+        check(lib().rr_refactor(self.handle, ctypes.c_void_p(_stream(stream))))
+
+    # -- Algorithm 1 ---------------------------------------------------------
+    def empty_block(self, k: int) -> torch.Tensor:
+        return torch.empty((self.n_omega, k, self.n), dtype=torch.complex128, device="cuda")
+
+    def sketch_solve(self, k: int, seed: int = 0, q: int = 0, out=None, stream=None):
+        Q = out if out is not None else self.empty_block(k)
+        check(lib().rr_sketch_solve(self.handle, k, seed, q, _ptr(Q),
+                                    ctypes.c_void_p(_stream(stream))))
+        return Q
+
+    def adjoint_solve(self, Q: torch.Tensor, out=None, stream=None):
+        k = Q.shape[1]
+        Z = out if out is not None else self.empty_block(k)
+        check(lib().rr_adjoint_solve(self.handle, k, _ptr(Q), _ptr(Z),
+                                     ctypes.c_void_p(_stream(stream))))
+        return Z
+
+    def solve(self, Bm: torch.Tensor, out=None, stream=None):
+        k = Bm.shape[1]
+        X = out if out is not None else self.empty_block(k)
+        check(lib().rr_solve(self.handle, k, _ptr(Bm), _ptr(X), ctypes.c_void_p(_stream(stream))))
+        return X
+
+    def gains(self, Q: Optional[torch.Tensor], Z: torch.Tensor, response: str = "av",
+              out: Optional[dict] = None, stream=None) -> dict:
+        k = Z.shape[1]
+        dev = "cuda"
+        o = out or {}
+        sB = o.get("sigma_B", torch.empty((self.n_omega, k), dtype=torch.float64, device=dev))
+        V = o.get("V", self.empty_block(k))
+        sAV = U = None
+        if response == "av":
+            sAV = o.get("sigma_AV", torch.empty((self.n_omega, k), dtype=torch.float64, device=dev))
+            U = o.get("U", self.empty_block(k))
+        elif response == "qu":
+            U = o.get("U", self.empty_block(k))
+        check(lib().rr_gains(self.handle, k, _ptr(Q) if Q is not None else None, _ptr(Z),
+                             RESPONSES[response], _ptr(sB), _ptr(sAV), _ptr(V), _ptr(U),
+                             ctypes.c_void_p(_stream(stream))))
+        return {"sigma_B": sB, "sigma_AV": sAV, "V": V, "U": U}
+
+    def grad(self, sigma1: torch.Tensor, u1: torch.Tensor, v1: torch.Tensor, stride: int,
+             stream=None):
+        """(dU (n_omega, nx, ny), dnu (n_omega,), domega (n_omega,)) of sigma_1."""
+        nx, ny = self.prob.nx, self.prob.ny
+        dU = torch.empty((self.n_omega, nx, ny), dtype=torch.float64, device="cuda")
+        dnu = torch.empty(self.n_omega, dtype=torch.float64, device="cuda")
+        dom = torch.empty(self.n_omega, dtype=torch.float64, device="cuda")
+        check(lib().rr_grad(self.handle, ctypes.c_void_p(sigma1.data_ptr()),
+                            ctypes.c_void_p(u1.data_ptr()), ctypes.c_void_p(v1.data_ptr()),
+                            stride, _ptr(dU), _ptr(dnu), _ptr(dom),
+                            ctypes.c_void_p(_stream(stream))))
+        return dU, dnu, dom
+
+
+def factor(prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32, **kw) -> Factors:
+    return Factors(prob, omegas, precision, k_max, **kw)
+
+
+def resolvent(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
+              precision: str = "fp64", response: str = "av", factors: Optional[Factors] = None,
+              check_status: bool = True, **kw) -> dict:
+    """Algorithm 1 for every shift: returns sigma_B, sigma_AV, V, U, Q (GPU tensors)."""
+    f = factors if factors is not None else factor(prob, omegas, precision, k_max=k, **kw)
+    Q = f.sketch_solve(k, seed, q)
+    Z = f.adjoint_solve(Q)
+    out = f.gains(Q, Z, response)
+    out["Q"] = Q
+    out["factors"] = f
+    if check_status:
+        f.check()
+    return out
+
+
+def philox_raw(count: int, c1: int = 0, c2: int = 0, key=(0, 0)) -> torch.Tensor:
+    """Raw Philox4x32-10 words from the device generator: (count, 4) uint32 as int64."""
+    out = torch.empty(4 * count, dtype=torch.int32, device="cuda")
+    check(lib().rr_philox_raw(_ptr(out), count, c1, c2, key[0], key[1],
+                              ctypes.c_void_p(_stream())))
+    return (out.to(torch.int64) & 0xFFFFFFFF).reshape(count, 4)
+
+
+def sketch(prob: BurgersProblem, k: int, seed: int = 0) -> torch.Tensor:
+    """The test matrix Theta (k, n) the sketch step draws (eq. 10 weighting)."""
+    out = torch.empty((k, prob.n), dtype=torch.complex128, device="cuda")
+    ps = prob.c_struct()
+    check(lib().rr_sketch(ctypes.byref(ps), k, seed, _ptr(out), ctypes.c_void_p(_stream())))
+    return out

@@ -1,0 +1,406 @@
+// Host side of the C ABI: argument checks, workspace ownership and the order
+// of launches for each call of Algorithm 1.  Every numerical step runs in the
+// kernels of rr_operator.hip, rr_band.hip, rr_small.hip and rr_grad.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "rr_internal.h"
+
+using namespace rr;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+rr_status fail(rr_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define RR_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(RR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+bool is_dev_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+template <typename T>
+rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(RR_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  f->bytes += bytes;
+  return RR_OK;
+}
+
+void free_all(rr_factors* f) {
+  void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->flags, f->ctrl, f->theta,
+                f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
+                f->small.Rinv, f->small.W, f->small.Ut, f->grad_partial};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+}
+
+OpDesc opdesc(const rr_factors* f) { return OpDesc{f->nx, f->ny, f->n, f->coef}; }
+
+uint32_t* st_word(rr_factors* f) { return f->ctrl; }
+uint32_t* ticket_word(rr_factors* f) { return f->ctrl + 1; }
+uint32_t* fail_word(rr_factors* f) { return f->ctrl + 2; }
+// ctrl[4 + it]: unconverged columns after correction it (mixed solves)
+constexpr int kMaxRefine = 16;
+
+__global__ void k_latch_if_nonzero(const uint32_t* count, uint32_t* status, uint32_t bit) {
+  if (threadIdx.x == 0 && *count) atomicOr(status, bit);
+}
+__global__ void k_record_max(const uint32_t* count, uint32_t* slot) {
+  if (threadIdx.x == 0) atomicMax(slot, *count);
+}
+
+// X = M^-1 Bm (or M^-H): one FP64 band solve, or FP32 solves with FP64
+// residual refinement.  Bm's blocks are bstride apart (0 = shared by all shifts).
+rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t bstride,
+                    double* X, hipStream_t s) {
+  const bool mixed = f->prec == RR_MIXED;
+  RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
+                      f->flags, ticket_word(f), st_word(f), f->grid, s));
+  if (!mixed) return RR_OK;
+  double* res = f->work3;
+  for (int it = 0; it < f->refine_iters; it++) {
+    // res = Bm - M X in FP64 from the stencil, then res <- M32^-1 res, X += res
+    RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, k, adjoint, X, Bm, bstride, res, s));
+    RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
+                        (int64_t)k * f->n, res, f->flags, ticket_word(f), st_word(f), f->grid, s));
+    RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
+    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, f->refine_tol, f->small, st_word(f),
+                                fail_word(f), s));
+    hipLaunchKernelGGL(k_record_max, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
+                       f->ctrl + 4 + it);
+  }
+  hipLaunchKernelGGL(k_latch_if_nonzero, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
+                     st_word(f), (uint32_t)ST_NOT_CONVERGED);
+  RR_HIP(hipGetLastError());
+  return RR_OK;
+}
+
+rr_status check_k(const rr_factors* f, int k) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  if (f->sticky_hip_error) return fail(RR_ERR_HIP, "handle is unusable after a HIP error");
+  if (k < 1 || k > f->k_max) return fail(RR_ERR_INVALID, "k must be in [1, k_max]");
+  return RR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rr_last_error(void) { return g_err.c_str(); }
+
+rr_status rr_burgers_coeffs(int32_t nx, int32_t ny, const double* U, double x0, double x1,
+                            double y0, double y1, double nu, double* coef_out, double* phi_out,
+                            void* stream) {
+  if (nx < 1 || ny < 1) return fail(RR_ERR_INVALID, "nx, ny must be >= 1");
+  if (!U || !coef_out) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (!(x1 > x0) || !(y1 > y0)) return fail(RR_ERR_INVALID, "empty domain");
+  double hx = (x1 - x0) / (nx + 1), hy = (y1 - y0) / (ny + 1);
+  RR_HIP(launch_burgers_coeffs(nx, ny, U, hx, hy, nu, coef_out, phi_out, (hipStream_t)stream));
+  return RR_OK;
+}
+
+rr_status rr_apply(const rr_problem* p, const double* omega_re, const double* omega_im,
+                   int32_t n_omega, int32_t k, int32_t adjoint, const double* X, double* Y,
+                   void* stream) {
+  if (!p || !p->coef || !X || !Y || !omega_re) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (p->nx < 1 || p->ny < 1 || n_omega < 1 || k < 1 || n_omega > 65535 || k > 65535)
+    return fail(RR_ERR_INVALID, "bad sizes");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> om(2 * n_omega);
+  for (int i = 0; i < n_omega; i++) {
+    om[2 * i] = omega_re[i];
+    om[2 * i + 1] = omega_im ? omega_im[i] : 0.0;
+  }
+  double* dom = nullptr;
+  RR_HIP(hipMalloc((void**)&dom, om.size() * sizeof(double)));
+  RR_HIP(hipMemcpyAsync(dom, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  OpDesc op{p->nx, p->ny, 2 * p->nx * p->ny, p->coef};
+  hipError_t e = launch_apply(op, dom, n_omega, k, adjoint, X, nullptr, 0, Y, s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(dom);
+  if (e != hipSuccess) return fail(RR_ERR_HIP, hipGetErrorString(e));
+  return RR_OK;
+}
+
+rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* omega_im,
+                    int32_t n_omega, int32_t k_max, rr_precision prec, const rr_tuning* tune,
+                    void* stream, rr_factors** out) {
+  if (!out) return fail(RR_ERR_INVALID, "NULL output handle pointer");
+  *out = nullptr;
+  if (!p || !p->coef || !omega_re) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (p->nx < 1 || p->ny < 1) return fail(RR_ERR_INVALID, "nx, ny must be >= 1");
+  if (n_omega < 1) return fail(RR_ERR_INVALID, "n_omega must be >= 1");
+  if (k_max < 1 || k_max > 32) return fail(RR_ERR_INVALID, "k_max must be in [1, 32]");
+  if (prec != RR_FP64 && prec != RR_MIXED) return fail(RR_ERR_INVALID, "unknown precision");
+  int64_t n64 = 2 * (int64_t)p->nx * p->ny;
+  if (n64 > (1ll << 30)) return fail(RR_ERR_INVALID, "operator too large");
+  if (k_max > n64) return fail(RR_ERR_INVALID, "k_max exceeds n");
+  for (int i = 0; i < n_omega; i++)
+    if (!std::isfinite(omega_re[i]) || (omega_im && !std::isfinite(omega_im[i])))
+      return fail(RR_ERR_INVALID, "non-finite omega");
+  int T = tune && tune->tile ? tune->tile : 64;
+  if (T != 32 && T != 64) return fail(RR_ERR_INVALID, "tile must be 32 or 64");
+  if (tune && (tune->refine_iters < 0 || tune->refine_iters > kMaxRefine))
+    return fail(RR_ERR_INVALID, "refine_iters out of range");
+  if (!is_dev_ptr(p->coef) || (p->phi && !is_dev_ptr(p->phi)) || (p->U && !is_dev_ptr(p->U)))
+    return fail(RR_ERR_INVALID, "coef/phi/U must be device pointers");
+
+  rr_factors* f = new rr_factors();
+  f->nx = p->nx;
+  f->ny = p->ny;
+  f->n = (int)n64;
+  f->n_omega = n_omega;
+  f->k_max = k_max;
+  f->prec = prec;
+  const int b = 2 * p->ny;
+  f->geom.T = T;
+  f->geom.B = (b + T - 1) / T;
+  f->geom.NB = (f->n + T - 1) / T;
+  f->grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
+  f->refine_iters = tune ? (tune->refine_iters ? tune->refine_iters : 3) : 3;
+  f->refine_tol = tune && tune->refine_tol > 0 ? tune->refine_tol : 1e-10;
+  f->omega_host.resize(2 * n_omega);
+  for (int i = 0; i < n_omega; i++) {
+    f->omega_host[2 * i] = omega_re[i];
+    f->omega_host[2 * i + 1] = omega_im ? omega_im[i] : 0.0;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nn = (size_t)p->nx * p->ny;
+  const size_t vec = (size_t)n_omega * k_max * f->n * 2 * sizeof(double);
+  const size_t elem = prec == RR_MIXED ? 2 * sizeof(float) : 2 * sizeof(double);
+  f->tile_bytes = (size_t)n_omega * f->geom.tiles_per_omega() * T * T * elem;
+  size_t nflags = std::max((size_t)n_omega * f->geom.tiles_per_omega(), (size_t)n_omega * f->geom.NB);
+  int nchunk = (f->n + 2047) / 2048;
+  size_t kk = (size_t)std::max(k_max * k_max, 64);
+  rr_status st = RR_OK;
+#define ALLOC(ptr, bytes)                      \
+  do {                                         \
+    st = dalloc(f, &(ptr), (bytes));           \
+    if (st != RR_OK) goto fail_free;           \
+  } while (0)
+  ALLOC(f->coef, nn * 12 * sizeof(double));
+  if (p->phi) ALLOC(f->phi, nn * sizeof(double));
+  if (p->U) ALLOC(f->U, (size_t)(p->nx + 2) * (p->ny + 2) * sizeof(double));
+  ALLOC(f->omega, 2 * n_omega * sizeof(double));
+  ALLOC(f->tiles, f->tile_bytes);
+  ALLOC(f->flags, nflags * sizeof(int));
+  f->flag_count = nflags;
+  ALLOC(f->ctrl, 64 * sizeof(uint32_t));
+  ALLOC(f->theta, (size_t)k_max * f->n * 2 * sizeof(double));
+  ALLOC(f->work1, vec);
+  ALLOC(f->work2, vec);
+  if (prec == RR_MIXED) ALLOC(f->work3, vec);
+  ALLOC(f->small.partial, (size_t)n_omega * nchunk * kk * 2 * sizeof(double));
+  ALLOC(f->small.G, (size_t)n_omega * kk * 2 * sizeof(double));
+  ALLOC(f->small.R, (size_t)n_omega * kk * 2 * sizeof(double));
+  ALLOC(f->small.Rinv, (size_t)n_omega * kk * 2 * sizeof(double));
+  ALLOC(f->small.W, (size_t)n_omega * kk * 2 * sizeof(double));
+  ALLOC(f->small.Ut, (size_t)n_omega * kk * 2 * sizeof(double));
+  f->small.nchunk = nchunk;
+  f->small.kmax = k_max;
+  f->grad_nchunk = (int)((nn + 255) / 256);
+  ALLOC(f->grad_partial, (size_t)n_omega * f->grad_nchunk * 2 * sizeof(double));
+#undef ALLOC
+  {
+    hipError_t e = hipMemcpyAsync(f->coef, p->coef, nn * 12 * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && p->phi)
+      e = hipMemcpyAsync(f->phi, p->phi, nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && p->U)
+      e = hipMemcpyAsync(f->U, p->U, (size_t)(p->nx + 2) * (p->ny + 2) * sizeof(double),
+                         hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(f->omega, f->omega_host.data(), 2 * n_omega * sizeof(double),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill_u32(f->ctrl, 0u, 64, s);
+    if (e != hipSuccess) {
+      st = fail(RR_ERR_HIP, hipGetErrorString(e));
+      goto fail_free;
+    }
+  }
+  if (p->U) {
+    if (!(p->x1 > p->x0) || !(p->y1 > p->y0)) {
+      st = fail(RR_ERR_INVALID, "empty domain");
+      goto fail_free;
+    }
+    f->hx = (p->x1 - p->x0) / (p->nx + 1);
+    f->hy = (p->y1 - p->y0) / (p->ny + 1);
+    f->nu = p->nu;
+    f->has_burgers = true;
+  }
+  st = rr_refactor(f, stream);
+  if (st != RR_OK) goto fail_free;
+  // the omega upload reads a host vector owned by the handle: nothing to wait for
+  *out = f;
+  return RR_OK;
+fail_free:
+  (void)hipStreamSynchronize(s);
+  free_all(f);
+  delete f;
+  return st;
+}
+
+rr_status rr_refactor(rr_factors* f, void* stream) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  if (f->sticky_hip_error) return fail(RR_ERR_HIP, "handle is unusable after a HIP error");
+  hipError_t e = launch_factor(opdesc(f), f->geom, f->omega, f->n_omega, f->prec == RR_MIXED,
+                               f->tiles, f->flags, ticket_word(f), st_word(f), f->grid,
+                               (hipStream_t)stream);
+  if (e != hipSuccess) {
+    f->sticky_hip_error = true;
+    return fail(RR_ERR_HIP, std::string("factor launch: ") + hipGetErrorString(e));
+  }
+  return RR_OK;
+}
+
+rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power_iters, double* Q,
+                          void* stream) {
+  rr_status st = check_k(f, k);
+  if (st != RR_OK) return st;
+  if (!Q) return fail(RR_ERR_INVALID, "NULL Q");
+  if (power_iters < 0 || power_iters > 64) return fail(RR_ERR_INVALID, "bad power_iters");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t blk = (int64_t)k * f->n;
+  RR_HIP(launch_fill_u32(f->ctrl + 4, 0u, kMaxRefine, s));
+  RR_HIP(launch_sketch(opdesc(f), f->phi, k, seed, f->theta, s));                   // step 1
+  if ((st = solve_any(f, k, 0, f->theta, 0, Q, s)) != RR_OK) return st;             // step 2
+  RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));       // step 3
+  for (int it = 0; it < power_iters; it++) {                                        // 2.2.1
+    if ((st = solve_any(f, k, 1, Q, blk, f->work1, s)) != RR_OK) return st;
+    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, f->work1, f->work1, f->small, st_word(f), s));
+    if ((st = solve_any(f, k, 0, f->work1, blk, Q, s)) != RR_OK) return st;
+    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));
+  }
+  return RR_OK;
+}
+
+rr_status rr_adjoint_solve(rr_factors* f, int32_t k, const double* Q, double* Z, void* stream) {
+  rr_status st = check_k(f, k);
+  if (st != RR_OK) return st;
+  if (!Q || !Z) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (Q == Z && f->prec == RR_MIXED) return fail(RR_ERR_INVALID, "Z may not alias Q (mixed)");
+  return solve_any(f, k, 1, Q, (int64_t)k * f->n, Z, (hipStream_t)stream);        // step 4
+}
+
+rr_status rr_solve(rr_factors* f, int32_t k, const double* Bm, double* X, void* stream) {
+  rr_status st = check_k(f, k);
+  if (st != RR_OK) return st;
+  if (!Bm || !X) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (Bm == X) return fail(RR_ERR_INVALID, "X may not alias Bm");
+  return solve_any(f, k, 0, Bm, (int64_t)k * f->n, X, (hipStream_t)stream);
+}
+
+rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z, rr_response mode,
+                   double* sigma_B, double* sigma_AV, double* V, double* Uresp, void* stream) {
+  rr_status st = check_k(f, k);
+  if (st != RR_OK) return st;
+  if (!Z || !sigma_B || !V) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (mode == RR_RESP_AV && !sigma_AV) return fail(RR_ERR_INVALID, "sigma_AV needed for AV");
+  if (mode == RR_RESP_QU && (!Q || !Uresp)) return fail(RR_ERR_INVALID, "Q, Uresp needed for QU");
+  if (mode != RR_RESP_AV && mode != RR_RESP_QU && mode != RR_RESP_NONE)
+    return fail(RR_ERR_INVALID, "unknown response mode");
+  if (V == Z || (Uresp && (Uresp == V || Uresp == Z)))
+    return fail(RR_ERR_INVALID, "outputs may not alias inputs");
+  hipStream_t s = (hipStream_t)stream;
+  // step 5 (and eq. 8 when asked)
+  RR_HIP(launch_small_svd(f->n, f->n_omega, k, Z, Q, sigma_B, V,
+                          mode == RR_RESP_QU ? Uresp : nullptr, f->small, st_word(f), s));
+  if (mode == RR_RESP_AV) {
+    // steps 6-9: W = M^-1 V, sigma_j = ||W_j||, u_j = W_j / sigma_j
+    double* W = Uresp ? Uresp : f->work2;
+    if ((st = solve_any(f, k, 0, V, (int64_t)k * f->n, W, s)) != RR_OK) return st;
+    RR_HIP(launch_colnorm_scale(f->n, f->n_omega, k, W, sigma_AV, Uresp, f->small, st_word(f), s));
+  }
+  return RR_OK;
+}
+
+rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const double* v1,
+                  int64_t vec_stride, double* dU, double* dnu, double* domega, void* stream) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  if (!f->has_burgers) return fail(RR_ERR_INVALID, "rr_grad needs the Burgers description (U)");
+  if (!sigma1 || !u1 || !v1 || !dU || !dnu || !domega) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (vec_stride < f->n && f->n_omega > 1) return fail(RR_ERR_INVALID, "vec_stride < n");
+  RR_HIP(launch_grad(f->nx, f->ny, f->hx, f->hy, f->n_omega, f->omega, sigma1, u1, v1, vec_stride,
+                     dU, dnu, domega, f->grad_partial, f->grad_nchunk, (hipStream_t)stream));
+  return RR_OK;
+}
+
+rr_status rr_check(rr_factors* f, void* stream) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    f->sticky_hip_error = true;
+    return fail(RR_ERR_HIP, std::string("stream: ") + hipGetErrorString(e));
+  }
+  uint32_t ctrl[4 + kMaxRefine];
+  e = hipMemcpy(ctrl, f->ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    f->sticky_hip_error = true;
+    return fail(RR_ERR_HIP, hipGetErrorString(e));
+  }
+  f->refine_used = 0;
+  if (f->prec == RR_MIXED) {
+    f->refine_used = f->refine_iters;
+    for (int it = 0; it < f->refine_iters; it++)
+      if (ctrl[4 + it] == 0) { f->refine_used = it + 1; break; }
+  }
+  uint32_t w = ctrl[0];
+  if (w) {
+    uint32_t zero = 0;
+    (void)hipMemcpy(f->ctrl, &zero, sizeof(zero), hipMemcpyHostToDevice);
+  }
+  if (w & ST_TIMEOUT) return fail(RR_ERR_TIMEOUT, "a dataflow wait timed out");
+  if (w & ST_SINGULAR) return fail(RR_ERR_SINGULAR, "zero or non-finite pivot in the band LU");
+  if (w & ST_NONFINITE) return fail(RR_ERR_NONFINITE, "non-finite values in the results");
+  if (w & ST_BREAKDOWN) return fail(RR_ERR_BREAKDOWN, "Gram matrix not positive definite");
+  if (w & ST_NOT_CONVERGED) return fail(RR_ERR_NOT_CONVERGED, "refinement did not converge");
+  return RR_OK;
+}
+
+int32_t rr_refine_count(rr_factors* f) { return f ? f->refine_used : 0; }
+
+size_t rr_bytes(const rr_factors* f) { return f ? f->bytes : 0; }
+
+void rr_factors_free(rr_factors* f) {
+  if (!f) return;
+  (void)hipDeviceSynchronize();
+  free_all(f);
+  delete f;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// Internal declarations shared by the HIP sources of librr.so (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/rr.h"
+
+namespace rr {
+
+// ---------------------------------------------------------------------------
+// Device status word (latched per handle, read by rr_check)
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+  ST_SINGULAR = 1u << 0,
+  ST_NOT_CONVERGED = 1u << 1,
+  ST_BREAKDOWN = 1u << 2,
+  ST_NONFINITE = 1u << 3,
+  ST_TIMEOUT = 1u << 4,
+};
+
+// Wall-clock bound of any dataflow wait (constant 100 MHz counter ticks).
+// A legitimate wait is shorter than one full factorisation; 20 s means a bug.
+constexpr uint64_t kWaitTicks = 20ull * 100000000ull;
+
+template <typename R>
+struct cplx {
+  R re, im;
+};
+
+__device__ __forceinline__ void latch(uint32_t* status, uint32_t bit) {
+  atomicOr(status, bit);
+}
+
+// Hard bound on polls of one wait, independent of the clock (a poll is one
+// device-coherent atomic plus a short sleep, i.e. at least ~1 us).
+constexpr uint32_t kWaitPolls = 1u << 25;
+
+// Agent-scope wait on a flag word set by another workgroup.  Thread 0 polls
+// with a relaxed atomic read-modify-write (performed device-coherently, so it
+// needs no cache invalidation per poll), then issues one acquire fence; the
+// workgroup barrier afterwards orders every thread's later loads.  Returns
+// false (and latches ST_TIMEOUT) if the wait bound is exceeded or a timeout was
+// already latched, so a broken dependency drains instead of hanging.
+__device__ __forceinline__ bool wg_wait_flag(int* flag, int want, uint32_t* status) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    int good = 1;
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT) {
+      good = 0;
+    } else {
+      uint64_t t0 = wall_clock64();
+      uint32_t polls = 0;
+      while (__hip_atomic_fetch_add(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++polls > kWaitPolls || wall_clock64() - t0 > kWaitTicks) {
+          latch(status, ST_TIMEOUT);
+          good = 0;
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Make this workgroup's global stores visible device-wide, then publish a flag.
+// The trailing barrier keeps thread 0's flag store and its next ticket fetch
+// (wg_ticket) in separate barrier intervals: with both guarded by the same
+// "thread 0" test and nothing convergent between them, the compiler may send
+// the other threads straight from here to the ticket barrier, which splits the
+// persistent loop so that only thread 0 ever leaves it to take a new ticket.
+__device__ __forceinline__ void wg_publish(int* flag, int value) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+}
+
+// Next ticket of a persistent launch, the same value in every thread.  The
+// leading barrier closes the previous task (its readers of *slot are done).
+__device__ __forceinline__ int64_t wg_ticket(uint32_t* counter, uint32_t* slot) {
+  __syncthreads();
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1u);
+  __syncthreads();
+  return (int64_t)__builtin_amdgcn_readfirstlane(*slot);
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers implemented in the .hip files
+// ---------------------------------------------------------------------------
+struct OpDesc {  // the operator on the device
+  int nx, ny, n;
+  const double* coef;
+};
+
+struct BandGeom {  // tile geometry of the band factor
+  int T;     // tile edge
+  int B;     // tiles per half-band: ceil(b / T)
+  int NB;    // block rows: ceil(n / T)
+  int64_t tiles_per_omega() const { return (int64_t)NB * (2 * B + 1); }
+};
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, double hy,
+                                 double nu, double* coef, double* phi, hipStream_t s);
+// Y = b - M X (residual) or Y = M X; adjoint applies M^H.  k columns per shift.
+// Bm's blocks are bstride elements apart (0: one block shared by every shift).
+hipError_t launch_apply(const OpDesc& op, const double* omega /*dev 2*n_omega*/, int n_omega,
+                        int k, int adjoint, const double* X, const double* Bm, int64_t bstride,
+                        double* Y, hipStream_t s);
+hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed,
+                         double* Theta, hipStream_t s);
+
+// Band LU: tiles = n_omega * NB * (2B+1) tiles of T*T complex (R = float|double)
+hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega,
+                         int n_omega, bool fp32, void* tiles, int* flags, uint32_t* ticket,
+                         uint32_t* status, int grid, hipStream_t s);
+// Multi-RHS solve with the band factor: X = M^-1 Bm (adjoint: M^-H Bm).
+// Bm's blocks are bstride complex elements apart (0: shared); Bm may alias X.
+hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
+                        const void* tiles, int adjoint, const double* Bm, int64_t bstride,
+                        double* X, int* flags, uint32_t* ticket, uint32_t* status, int grid,
+                        hipStream_t s);
+
+// Small dense / tall-skinny kernels (rr_small.hip)
+struct SmallWs {   // workspace for tall-skinny reductions
+  double* partial;     // n_omega * nchunk * kmax*kmax complex
+  double* G;           // n_omega * kmax*kmax complex
+  double* R;           // n_omega * kmax*kmax complex (upper triangular factor)
+  double* Rinv;        // n_omega * kmax*kmax complex (applied matrix)
+  double* W;           // n_omega * kmax*kmax complex (SVD right vectors)
+  double* Ut;          // n_omega * kmax*kmax complex (SVD left vectors)
+  int nchunk;
+  int kmax;
+};
+// CholQR2: Q = Y R^-1 with R upper, real positive diagonal; Q may alias Y.
+hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q,
+                          SmallWs& ws, uint32_t* status, hipStream_t s);
+// Z = Qz R (CholQR2); SVD of R^H = Ut S W^H; sigma = S; V = Z R^-1 W;
+// if Uqu != NULL also Uqu = Q Ut.
+hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const double* Q,
+                            double* sigma, double* V, double* Uqu, SmallWs& ws,
+                            uint32_t* status, hipStream_t s);
+// sigma_j = ||W_j||, U_j = W_j / sigma_j  (W may alias U)
+hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, double* sigma,
+                                double* U, SmallWs& ws, uint32_t* status, hipStream_t s);
+// X += D and per-column convergence test ||D_j|| <= tol ||X_j|| (latches status)
+hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D,
+                                double tol, SmallWs& ws, uint32_t* status,
+                                uint32_t* fail_count, hipStream_t s);
+// gradient kernel (rr_grad.hip)
+hipError_t launch_grad(int nx, int ny, double hx, double hy, int n_omega,
+                       const double* omega, const double* sigma1, const double* u1,
+                       const double* v1, int64_t stride, double* dU, double* dnu,
+                       double* domega, double* partial, int nchunk, hipStream_t s);
+
+}  // namespace rr
+
+// ---------------------------------------------------------------------------
+// The handle
+// ---------------------------------------------------------------------------
+struct rr_factors {
+  int nx, ny, n, n_omega, k_max;
+  rr_precision prec;
+  rr::BandGeom geom;
+  int grid;
+  int refine_iters;
+  double refine_tol;
+  // private copies of the problem
+  double* coef = nullptr;
+  double* phi = nullptr;
+  double* U = nullptr;
+  double hx = 0, hy = 0, nu = 0;
+  bool has_burgers = false;
+  double* omega = nullptr;            // device, 2*n_omega (re, im)
+  std::vector<double> omega_host;     // 2*n_omega
+  // factors and dataflow state
+  void* tiles = nullptr;
+  size_t tile_bytes = 0;
+  int* flags = nullptr;               // max(factor flags, solve flags)
+  size_t flag_count = 0;
+  uint32_t* ctrl = nullptr;           // [0] status, [1] ticket, [2] refine fails
+  // vector workspaces (n_omega*k_max*n complex each unless noted)
+  double* theta = nullptr;            // k_max*n (shared by all shifts)
+  double* work1 = nullptr;
+  double* work2 = nullptr;
+  double* work3 = nullptr;
+  rr::SmallWs small{};
+  double* grad_partial = nullptr;
+  int grad_nchunk = 0;
+  size_t bytes = 0;
+  int refine_used = 0;
+  bool sticky_hip_error = false;
+};

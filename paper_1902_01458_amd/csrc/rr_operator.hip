@@ -1,0 +1,213 @@
+// Operator-side kernels: Burgers stencil coefficients, matrix-free M X in
+// FP64 (residuals of the mixed-precision refinement), and the physics-weighted
+// complex Gaussian sketch (Algorithm 1 step 1 with eq. 10 weighting).
+#include "rr_internal.h"
+
+namespace rr {
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+// Linearised viscous Burgers about (U(x,y), V = 0), central differences:
+//   u-row: nu Lap u - U u_x - U_x u - U_y v,    v-row: nu Lap v - U v_x
+__global__ void k_burgers_coeffs(int nx, int ny, const double* __restrict__ U, double hx,
+                                 double hy, double nu, double* __restrict__ coef,
+                                 double* __restrict__ phi) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nx * ny) return;
+  int i = p / ny + 1, j = p % ny + 1;  // 1-based node in the (nx+2) x (ny+2) array
+  int ld = ny + 2;
+  double Uc = U[i * ld + j];
+  double Ux = (U[(i + 1) * ld + j] - U[(i - 1) * ld + j]) / (2.0 * hx);
+  double Uy = (U[i * ld + j + 1] - U[i * ld + j - 1]) / (2.0 * hy);
+  double ax = nu / (hx * hx), ay = nu / (hy * hy);
+  double* c = coef + 12 * (int64_t)p;
+  c[0] = -2.0 * (ax + ay) - Ux;
+  c[1] = ax - Uc / (2.0 * hx);
+  c[2] = ax + Uc / (2.0 * hx);
+  c[3] = ay;
+  c[4] = ay;
+  c[5] = -Uy;
+  c[6] = -2.0 * (ax + ay);
+  c[7] = ax - Uc / (2.0 * hx);
+  c[8] = ax + Uc / (2.0 * hx);
+  c[9] = ay;
+  c[10] = ay;
+  c[11] = 0.0;
+  if (phi) phi[p] = sqrt(Ux * Ux + Uy * Uy) + 0.1;
+}
+
+hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, double hy,
+                                 double nu, double* coef, double* phi, hipStream_t s) {
+  int nn = nx * ny;
+  hipLaunchKernelGGL(k_burgers_coeffs, dim3((nn + 255) / 256), dim3(256), 0, s, nx, ny, U, hx,
+                     hy, nu, coef, phi);
+  return hipGetLastError();
+}
+
+// Y = Bm - M X  (or Y = M X when Bm == NULL), M = i omega I - L, for one
+// column j (blockIdx.y) of shift w (blockIdx.z); one thread per node (both
+// components).  Adjoint: M^H = conj(i omega) I - L^T, whose stencil reads the
+// transposed coefficients from the neighbouring nodes.
+__global__ void k_apply(int nx, int ny, const double* __restrict__ coef,
+                        const double* __restrict__ omega, int k, int adjoint,
+                        const double2* __restrict__ X, const double2* __restrict__ Bm,
+                        int64_t bstride, double2* __restrict__ Y) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  int nn = nx * ny;
+  if (p >= nn) return;
+  int j = blockIdx.y, w = blockIdx.z;
+  int64_t n = 2 * (int64_t)nn;
+  int64_t off = ((int64_t)w * k + j) * n;
+  const double2* x = X + off;
+  int i = p / ny, jj = p % ny;
+  bool hE = i < nx - 1, hW = i > 0, hN = jj < ny - 1, hS = jj > 0;
+  int pE = p + ny, pW = p - ny, pN = p + 1, pS = p - 1;
+  const double* c = coef + 12 * (int64_t)p;
+  double2 xu = x[2 * p], xv = x[2 * p + 1];
+  double lu_r, lu_i, lv_r, lv_i;  // (L x) or (L^T x) at rows 2p, 2p+1
+  if (!adjoint) {
+    lu_r = c[0] * xu.x + c[5] * xv.x;
+    lu_i = c[0] * xu.y + c[5] * xv.y;
+    lv_r = c[6] * xv.x + c[11] * xu.x;
+    lv_i = c[6] * xv.y + c[11] * xu.y;
+    if (hE) { double2 a = x[2 * pE], b = x[2 * pE + 1];
+      lu_r += c[1] * a.x; lu_i += c[1] * a.y; lv_r += c[7] * b.x; lv_i += c[7] * b.y; }
+    if (hW) { double2 a = x[2 * pW], b = x[2 * pW + 1];
+      lu_r += c[2] * a.x; lu_i += c[2] * a.y; lv_r += c[8] * b.x; lv_i += c[8] * b.y; }
+    if (hN) { double2 a = x[2 * pN], b = x[2 * pN + 1];
+      lu_r += c[3] * a.x; lu_i += c[3] * a.y; lv_r += c[9] * b.x; lv_i += c[9] * b.y; }
+    if (hS) { double2 a = x[2 * pS], b = x[2 * pS + 1];
+      lu_r += c[4] * a.x; lu_i += c[4] * a.y; lv_r += c[10] * b.x; lv_i += c[10] * b.y; }
+  } else {
+    // (L^T x)_{2p} = uC_p xu_p + vCpl_p xv_p + uE_W xu_W + uW_E xu_E + uN_S xu_S + uS_N xu_N
+    lu_r = c[0] * xu.x + c[11] * xv.x;
+    lu_i = c[0] * xu.y + c[11] * xv.y;
+    lv_r = c[6] * xv.x + c[5] * xu.x;
+    lv_i = c[6] * xv.y + c[5] * xu.y;
+    if (hW) { const double* cw = coef + 12 * (int64_t)pW; double2 a = x[2 * pW], b = x[2 * pW + 1];
+      lu_r += cw[1] * a.x; lu_i += cw[1] * a.y; lv_r += cw[7] * b.x; lv_i += cw[7] * b.y; }
+    if (hE) { const double* ce = coef + 12 * (int64_t)pE; double2 a = x[2 * pE], b = x[2 * pE + 1];
+      lu_r += ce[2] * a.x; lu_i += ce[2] * a.y; lv_r += ce[8] * b.x; lv_i += ce[8] * b.y; }
+    if (hS) { const double* cs = coef + 12 * (int64_t)pS; double2 a = x[2 * pS], b = x[2 * pS + 1];
+      lu_r += cs[3] * a.x; lu_i += cs[3] * a.y; lv_r += cs[9] * b.x; lv_i += cs[9] * b.y; }
+    if (hN) { const double* cn = coef + 12 * (int64_t)pN; double2 a = x[2 * pN], b = x[2 * pN + 1];
+      lu_r += cn[4] * a.x; lu_i += cn[4] * a.y; lv_r += cn[10] * b.x; lv_i += cn[10] * b.y; }
+  }
+  // shift: M = (i omega) I - L; i omega = -om_i + i om_r; M^H shift = conj of it
+  double sr = -omega[2 * w + 1], si = adjoint ? -omega[2 * w] : omega[2 * w];
+  double2 mu, mv;
+  mu.x = sr * xu.x - si * xu.y - lu_r;
+  mu.y = sr * xu.y + si * xu.x - lu_i;
+  mv.x = sr * xv.x - si * xv.y - lv_r;
+  mv.y = sr * xv.y + si * xv.x - lv_i;
+  double2* y = Y + off;
+  if (Bm) {
+    const double2* b = Bm + (int64_t)w * bstride + (int64_t)j * n;
+    double2 bu = b[2 * p], bv = b[2 * p + 1];
+    mu.x = bu.x - mu.x; mu.y = bu.y - mu.y;
+    mv.x = bv.x - mv.x; mv.y = bv.y - mv.y;
+  }
+  y[2 * p] = mu;
+  y[2 * p + 1] = mv;
+}
+
+hipError_t launch_apply(const OpDesc& op, const double* omega, int n_omega, int k, int adjoint,
+                        const double* X, const double* Bm, int64_t bstride, double* Y,
+                        hipStream_t s) {
+  int nn = op.nx * op.ny;
+  dim3 grid((nn + 255) / 256, k, n_omega);
+  hipLaunchKernelGGL(k_apply, grid, dim3(256), 0, s, op.nx, op.ny, op.coef, omega, k, adjoint,
+                     (const double2*)X, (const double2*)Bm, bstride, (double2*)Y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64 products
+// on counter words 0 and 2, with the key bumped by the Weyl constants.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+__global__ void k_philox_raw(uint32_t* out, int64_t count, uint32_t c1, uint32_t c2,
+                             uint32_t k0, uint32_t k1) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t c[4] = {(uint32_t)i, c1, c2, 0u};
+  philox4x32_10(c, k0, k1);
+  out[4 * i + 0] = c[0]; out[4 * i + 1] = c[1]; out[4 * i + 2] = c[2]; out[4 * i + 3] = c[3];
+}
+
+// Theta[j][r] = phi[r/2] * sqrt(-ln u1) * exp(2 pi i u2), u1 = (m1+1) 2^-53,
+// u2 = m2 2^-53 from the top 53 bits of (x0:x1) and (x2:x3) at counter (r, j, 0, 0).
+__global__ void k_sketch(int64_t n, int k, const double* __restrict__ phi, uint32_t k0,
+                         uint32_t k1, double2* __restrict__ theta) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (r >= n) return;
+  uint32_t c[4] = {(uint32_t)r, (uint32_t)j, 0u, 0u};
+  philox4x32_10(c, k0, k1);
+  uint64_t m1 = ((((uint64_t)c[0]) << 32) | c[1]) >> 11;
+  uint64_t m2 = ((((uint64_t)c[2]) << 32) | c[3]) >> 11;
+  const double two_m53 = 1.1102230246251565404e-16;
+  double u1 = ((double)m1 + 1.0) * two_m53;
+  double u2 = (double)m2 * two_m53;
+  double rad = sqrt(-log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  double w = phi ? phi[r >> 1] : 1.0;
+  theta[(int64_t)j * n + r] = make_double2(w * rad * cs, w * rad * sn);
+}
+
+hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed,
+                         double* Theta, hipStream_t s) {
+  int64_t n = op.n;
+  dim3 grid((unsigned)((n + 255) / 256), k);
+  hipLaunchKernelGGL(k_sketch, grid, dim3(256), 0, s, n, k, phi, (uint32_t)(seed & 0xffffffffu),
+                     (uint32_t)(seed >> 32), (double2*)Theta);
+  return hipGetLastError();
+}
+
+}  // namespace rr
+
+// Raw generator output for the known-answer test of the device generator:
+// out[4*i .. 4*i+3] = Philox4x32-10 of counter (i, c1, c2, 0) under (k0, k1).
+extern "C" rr_status rr_philox_raw(uint32_t* out_dev, int64_t count, uint32_t c1, uint32_t c2,
+                                   uint32_t k0, uint32_t k1, void* stream) {
+  if (!out_dev || count < 0) return RR_ERR_INVALID;
+  if (count == 0) return RR_OK;
+  hipLaunchKernelGGL(rr::k_philox_raw, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, out_dev, count, c1, c2, k0, k1);
+  return hipGetLastError() == hipSuccess ? RR_OK : RR_ERR_HIP;
+}
+
+// Unweighted/weighted sketch written to a caller buffer (tests): Theta (k, n).
+extern "C" rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, double* theta,
+                               void* stream) {
+  if (!p || !theta || k < 1 || p->nx < 1 || p->ny < 1) return RR_ERR_INVALID;
+  rr::OpDesc op{p->nx, p->ny, 2 * p->nx * p->ny, p->coef};
+  return rr::launch_sketch(op, p->phi, k, seed, theta, (hipStream_t)stream) == hipSuccess
+             ? RR_OK
+             : RR_ERR_HIP;
+}

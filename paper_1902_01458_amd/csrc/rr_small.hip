@@ -1,0 +1,484 @@
+// Tall-skinny and k x k kernels (all FP64): Cholesky QR applied twice for the
+// orthonormal basis of Algorithm 1 step 3, the reduced SVD of step 5 (one-sided
+// Jacobi on the k x k triangular factor), the tall-small products that form
+// V = Qz W and U = Q Ut (eq. 8), the column norms of steps 7-9 and the
+// convergence test of the mixed-precision refinement.
+//
+// Reductions over n use a fixed chunking and a fixed summation order, so the
+// results are bitwise reproducible from run to run.
+#include "rr_internal.h"
+
+namespace rr {
+
+constexpr int kChunkRows = 2048;  // rows per partial-sum chunk
+constexpr int kSub = 64;          // rows staged in LDS at a time
+constexpr int KM = 32;            // largest sketch width the k x k kernels take
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// partial[w][chunk] = (Y_c T)^H (Y_c T) over the chunk's rows, where T is the
+// k x k matrix Tm[w] (identity when Tm == NULL).  Y: (n_omega, k, n).
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const double2* __restrict__ Y,
+                                                      const double2* __restrict__ Tm, int kmax,
+                                                      int nchunk, double2* __restrict__ partial) {
+  __shared__ double2 ys[kSub][KM + 1];
+  __shared__ double2 tm[KM][KM];
+  const int w = blockIdx.y, chunk = blockIdx.x;
+  const double2* Yw = Y + (int64_t)w * k * n;
+  if (Tm) {
+    for (int idx = threadIdx.x; idx < k * k; idx += 256)
+      tm[idx / k][idx % k] = Tm[(int64_t)w * kmax * kmax + idx];  // tm[i][j] = T[i][j]
+  }
+  const int npairs = k * k;
+  double2 acc[4];
+  for (int q = 0; q < 4; q++) acc[q] = make_double2(0, 0);
+  int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
+  for (int64_t rb = r0; rb < r1; rb += kSub) {
+    int rows = (int)min((int64_t)kSub, r1 - rb);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kSub * k; idx += 256) {
+      int j = idx / kSub, rr = idx % kSub;
+      ys[rr][j] = rr < rows ? Yw[(int64_t)j * n + rb + rr] : make_double2(0, 0);
+    }
+    __syncthreads();
+    if (Tm) {  // ys <- ys * T, one row per thread
+      double2 tmp[KM];
+      for (int rr = threadIdx.x; rr < kSub; rr += 256) {
+        for (int j = 0; j < k; j++) {
+          double2 s = make_double2(0, 0);
+          for (int i = 0; i < k; i++) {
+            double2 p = cmul(ys[rr][i], tm[i][j]);
+            s.x += p.x; s.y += p.y;
+          }
+          tmp[j] = s;
+        }
+        for (int j = 0; j < k; j++) ys[rr][j] = tmp[j];
+      }
+      __syncthreads();
+    }
+    for (int q = 0; q < 4; q++) {
+      int pr = threadIdx.x + 256 * q;
+      if (pr >= npairs) break;
+      int i = pr / k, j = pr % k;
+      double2 s = acc[q];
+      for (int rr = 0; rr < rows; rr++) {
+        double2 p = cmulc(ys[rr][i], ys[rr][j]);
+        s.x += p.x; s.y += p.y;
+      }
+      acc[q] = s;
+    }
+  }
+  for (int q = 0; q < 4; q++) {
+    int pr = threadIdx.x + 256 * q;
+    if (pr >= npairs) break;
+    partial[((int64_t)w * nchunk + chunk) * kmax * kmax + pr] = acc[q];
+  }
+}
+
+// Sum the partials (fixed order), Cholesky G = R^H R (R upper, real positive
+// diagonal), Rinv = R^-1.  compose != 0: R <- Rnew Rold, Rinv <- Rinv_old Rinv_new.
+__global__ __launch_bounds__(256) void k_chol(int k, int kmax, int nchunk,
+                                              const double2* __restrict__ partial,
+                                              double2* __restrict__ Rg, double2* __restrict__ Rinvg,
+                                              int compose, uint32_t* status) {
+  __shared__ double2 G[KM][KM + 1];
+  __shared__ double2 Rn[KM][KM + 1];
+  __shared__ double2 Ri[KM][KM + 1];
+  __shared__ int bad;
+  const int w = blockIdx.x;
+  for (int pr = threadIdx.x; pr < k * k; pr += 256) {
+    double2 s = make_double2(0, 0);
+    for (int c = 0; c < nchunk; c++) {
+      double2 v = partial[((int64_t)w * nchunk + c) * kmax * kmax + pr];
+      s.x += v.x; s.y += v.y;
+    }
+    G[pr / k][pr % k] = s;
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  // right-looking Cholesky on the upper triangle: G = R^H R
+  for (int j = 0; j < k; j++) {
+    if (threadIdx.x == 0) {
+      double d = G[j][j].x;
+      if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
+      G[j][j] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    double rjj = G[j][j].x;
+    for (int c = j + 1 + threadIdx.x; c < k; c += 256) {
+      G[j][c].x /= rjj; G[j][c].y /= rjj;
+    }
+    __syncthreads();
+    int wd = k - 1 - j;
+    for (int idx = threadIdx.x; idx < wd * wd; idx += 256) {
+      int a = j + 1 + idx / wd, c = j + 1 + idx % wd;
+      if (c < a) continue;
+      double2 p = cmulc(G[j][a], G[j][c]);  // R[j][a]^* R[j][c]
+      G[a][c].x -= p.x; G[a][c].y -= p.y;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+    int a = idx / k, c = idx % k;
+    Rn[a][c] = c >= a ? G[a][c] : make_double2(0, 0);
+    Ri[a][c] = make_double2(a == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  // Rinv: solve R X = I by back substitution, one column per thread
+  for (int c = threadIdx.x; c < k; c += 256) {
+    for (int a = c; a >= 0; a--) {
+      double2 s = make_double2(a == c ? 1.0 : 0.0, 0.0);
+      for (int t = a + 1; t <= c; t++) {
+        double2 p = cmul(Rn[a][t], Ri[t][c]);
+        s.x -= p.x; s.y -= p.y;
+      }
+      double d = Rn[a][a].x;
+      Ri[a][c] = make_double2(s.x / d, s.y / d);
+    }
+  }
+  __syncthreads();
+  double2* Rw = Rg + (int64_t)w * kmax * kmax;
+  double2* Riw = Rinvg + (int64_t)w * kmax * kmax;
+  if (compose) {
+    // R <- Rn * Rold ; Rinv <- Riold * Ri  (Rold, Riold are the global inputs)
+    double2 nr[4], ni[4];
+    for (int q = 0; q < 4; q++) {
+      int idx = threadIdx.x + 256 * q;
+      if (idx >= k * k) break;
+      int a = idx / k, c = idx % k;
+      double2 s = make_double2(0, 0), t2 = make_double2(0, 0);
+      for (int t = 0; t < k; t++) {
+        double2 p = cmul(Rn[a][t], Rw[t * k + c]);
+        s.x += p.x; s.y += p.y;
+        double2 q2 = cmul(Riw[a * k + t], Ri[t][c]);
+        t2.x += q2.x; t2.y += q2.y;
+      }
+      nr[q] = s;
+      ni[q] = t2;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; q++) {
+      int idx = threadIdx.x + 256 * q;
+      if (idx >= k * k) break;
+      Rw[idx] = nr[q];
+      Riw[idx] = ni[q];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+      Rw[idx] = Rn[idx / k][idx % k];
+      Riw[idx] = Ri[idx / k][idx % k];
+    }
+  }
+  if (threadIdx.x == 0 && bad) latch(status, ST_BREAKDOWN);
+}
+
+// Out = Y * Tm[w]  (n x k times k x k), one row per thread; Out may alias Y.
+__global__ __launch_bounds__(256) void k_apply_small(int64_t n, int k, const double2* Y,
+                                                     const double2* __restrict__ Tm, int kmax,
+                                                     double2* Out) {
+  __shared__ double2 tm[KM][KM];
+  const int w = blockIdx.y;
+  for (int idx = threadIdx.x; idx < k * k; idx += 256)
+    tm[idx / k][idx % k] = Tm[(int64_t)w * kmax * kmax + idx];
+  __syncthreads();
+  int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (r >= n) return;
+  const double2* Yw = Y + (int64_t)w * k * n;
+  double2* Ow = Out + (int64_t)w * k * n;
+  double2 row[KM];
+  for (int i = 0; i < k; i++) row[i] = Yw[(int64_t)i * n + r];
+  for (int j = 0; j < k; j++) {
+    double2 s = make_double2(0, 0);
+    for (int i = 0; i < k; i++) {
+      double2 p = cmul(row[i], tm[i][j]);
+      s.x += p.x; s.y += p.y;
+    }
+    Ow[(int64_t)j * n + r] = s;
+  }
+}
+
+static int nchunks(int64_t n) { return (int)((n + kChunkRows - 1) / kChunkRows); }
+
+hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q, SmallWs& ws,
+                          uint32_t* status, hipStream_t s) {
+  int nc = nchunks(n);
+  if (nc > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
+  dim3 g(nc, n_omega);
+  double2* part = (double2*)ws.partial;
+  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Y,
+                     (const double2*)nullptr, ws.kmax, nc, part);
+  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
+                     (double2*)ws.R, (double2*)ws.Rinv, 0, status);
+  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Y,
+                     (const double2*)ws.Rinv, ws.kmax, nc, part);
+  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
+                     (double2*)ws.R, (double2*)ws.Rinv, 1, status);
+  hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
+                     (int64_t)n, k, (const double2*)Y, (const double2*)ws.Rinv, ws.kmax,
+                     (double2*)Q);
+  return hipGetLastError();
+}
+
+// One-sided (Hestenes) Jacobi SVD of A = R^H (k x k, one workgroup per shift):
+// columns are rotated pairwise until mutually orthogonal, A J = Ut S, so
+// R^H = Ut S J^H.  Pairs follow the round-robin (circle) order, k/2 disjoint
+// pairs per round, 8 threads per pair.  Outputs sorted by descending sigma.
+// Also forms Tv = Rinv * W for V = Z Tv.
+__global__ __launch_bounds__(256) void k_jacobi_svd(int k, int kmax, const double2* __restrict__ Rg,
+                                                    const double2* __restrict__ Rinvg,
+                                                    double* __restrict__ sigma,
+                                                    double2* __restrict__ Utg, double2* __restrict__ Wg,
+                                                    double2* __restrict__ Tvg, uint32_t* status) {
+  __shared__ double2 A[KM][KM + 1];  // A[row][col]
+  __shared__ double2 J[KM][KM + 1];
+  __shared__ double sv[KM];
+  __shared__ int perm[KM];
+  __shared__ int rotated;
+  const int w = blockIdx.x;
+  const double2* R = Rg + (int64_t)w * kmax * kmax;
+  const int m = (k + 1) & ~1;  // even number of players (a zero column pads odd k)
+  for (int idx = threadIdx.x; idx < m * m; idx += 256) {
+    int a = idx / m, c = idx % m;
+    double2 v = make_double2(0, 0);
+    if (a < k && c < k) { double2 rc = R[c * k + a]; v = make_double2(rc.x, -rc.y); }  // R^H
+    A[a][c] = v;
+    J[a][c] = make_double2(a == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int npair = m / 2;
+  const int pair = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  for (int sweep = 0; sweep < 40; sweep++) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < m - 1; rnd++) {
+      if (pair < npair) {
+        int p, q;
+        if (pair == 0) { p = 0; q = 1 + rnd % (m - 1); }
+        else {
+          p = 1 + (pair + rnd) % (m - 1);
+          q = 1 + (m - 1 - pair + rnd) % (m - 1);
+        }
+        if (p > q) { int t = p; p = q; q = t; }
+        double al = 0, be = 0, gr = 0, gi = 0;
+        for (int a = sub; a < m; a += 8) {
+          double2 x = A[a][p], y = A[a][q];
+          al += x.x * x.x + x.y * x.y;
+          be += y.x * y.x + y.y * y.y;
+          gr += x.x * y.x + x.y * y.y;  // conj(x) y
+          gi += x.x * y.y - x.y * y.x;
+        }
+        for (int o = 1; o < 8; o <<= 1) {
+          al += __shfl_xor(al, o, 8);
+          be += __shfl_xor(be, o, 8);
+          gr += __shfl_xor(gr, o, 8);
+          gi += __shfl_xor(gi, o, 8);
+        }
+        double g = sqrt(gr * gr + gi * gi);
+        if (g > 1e-15 * sqrt(al * be) && g > 0.0) {
+          // phase e^{i phi} = gamma/|gamma|; rotate [a_p, e^{-i phi} a_q]
+          double er = gr / g, ei = -gi / g;  // e^{-i phi}
+          double zeta = (be - al) / (2.0 * g);
+          double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          for (int a = sub; a < m; a += 8) {
+            double2 x = A[a][p], y = A[a][q];
+            double2 yp = make_double2(y.x * er - y.y * ei, y.x * ei + y.y * er);
+            A[a][p] = make_double2(c * x.x - sn * yp.x, c * x.y - sn * yp.y);
+            A[a][q] = make_double2(sn * x.x + c * yp.x, sn * x.y + c * yp.y);
+            x = J[a][p]; y = J[a][q];
+            yp = make_double2(y.x * er - y.y * ei, y.x * ei + y.y * er);
+            J[a][p] = make_double2(c * x.x - sn * yp.x, c * x.y - sn * yp.y);
+            J[a][q] = make_double2(sn * x.x + c * yp.x, sn * x.y + c * yp.y);
+          }
+          if (sub == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < k; c += 256) {
+    double s = 0;
+    for (int a = 0; a < k; a++) s += A[a][c].x * A[a][c].x + A[a][c].y * A[a][c].y;
+    sv[c] = sqrt(s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < k; c++) perm[c] = c;
+    for (int a = 0; a < k; a++) {  // selection sort, descending, stable
+      int best = a;
+      for (int c = a + 1; c < k; c++)
+        if (sv[perm[c]] > sv[perm[best]]) best = c;
+      int t = perm[a]; perm[a] = perm[best]; perm[best] = t;
+    }
+    for (int c = 0; c < k; c++)
+      if (!isfinite(sv[c])) latch(status, ST_NONFINITE);
+  }
+  __syncthreads();
+  double* sw = sigma + (int64_t)w * k;
+  double2* Ut = Utg + (int64_t)w * kmax * kmax;
+  double2* Wm = Wg + (int64_t)w * kmax * kmax;
+  double2* Tv = Tvg + (int64_t)w * kmax * kmax;
+  const double2* Ri = Rinvg + (int64_t)w * kmax * kmax;
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+    int a = idx / k, c = idx % k;  // row a, output column c
+    int src = perm[c];
+    double s = sv[src];
+    double2 u = A[a][src];
+    Ut[a * k + c] = s > 0 ? make_double2(u.x / s, u.y / s) : make_double2(0, 0);
+    Wm[a * k + c] = J[a][src];
+    double2 t = make_double2(0, 0);
+    for (int b = 0; b < k; b++) {
+      double2 p = cmul(Ri[a * k + b], J[b][src]);
+      t.x += p.x; t.y += p.y;
+    }
+    Tv[a * k + c] = t;
+    if (a == 0) sw[c] = s;
+  }
+}
+
+hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const double* Q,
+                            double* sigma, double* V, double* Uqu, SmallWs& ws, uint32_t* status,
+                            hipStream_t s) {
+  int nc = nchunks(n);
+  if (nc > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
+  dim3 g(nc, n_omega);
+  double2* part = (double2*)ws.partial;
+  // Z = Qz R by two Cholesky QR passes (R and R^-1 composed; Qz never formed)
+  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Z,
+                     (const double2*)nullptr, ws.kmax, nc, part);
+  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
+                     (double2*)ws.R, (double2*)ws.Rinv, 0, status);
+  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Z,
+                     (const double2*)ws.Rinv, ws.kmax, nc, part);
+  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
+                     (double2*)ws.R, (double2*)ws.Rinv, 1, status);
+  // W and its product with R^-1 (ws.G holds Tv = R^-1 W)
+  hipLaunchKernelGGL(k_jacobi_svd, dim3(n_omega), dim3(256), 0, s, k, ws.kmax,
+                     (const double2*)ws.R, (const double2*)ws.Rinv, sigma, (double2*)ws.Ut,
+                     (double2*)ws.W, (double2*)ws.G, status);
+  // V = Z R^-1 W = Qz W
+  hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
+                     (int64_t)n, k, (const double2*)Z, (const double2*)ws.G, ws.kmax, (double2*)V);
+  if (Uqu)  // Halko et al.'s response modes U = Q Ut (eq. 8)
+    hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
+                       (int64_t)n, k, (const double2*)Q, (const double2*)ws.Ut, ws.kmax,
+                       (double2*)Uqu);
+  return hipGetLastError();
+}
+
+// partial[w][chunk][j] = sum over the chunk of |X_j|^2 (and of |D_j|^2 into
+// partial2 when D != NULL, after X += D).
+__global__ __launch_bounds__(256) void k_colnorm_partial(int64_t n, int k, double2* X,
+                                                         const double2* __restrict__ D,
+                                                         int nchunk, double* partial,
+                                                         double* partial2) {
+  __shared__ double red[2][256];
+  const int w = blockIdx.y, chunk = blockIdx.x;
+  int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
+  for (int j = 0; j < k; j++) {
+    double2* x = X + ((int64_t)w * k + j) * n;
+    const double2* d = D ? D + ((int64_t)w * k + j) * n : nullptr;
+    double sx = 0, sd = 0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+      double2 v = x[r];
+      if (d) {
+        double2 dv = d[r];
+        sd += dv.x * dv.x + dv.y * dv.y;
+        v.x += dv.x; v.y += dv.y;
+        x[r] = v;
+      }
+      sx += v.x * v.x + v.y * v.y;
+    }
+    red[0][threadIdx.x] = sx;
+    red[1][threadIdx.x] = sd;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      partial[((int64_t)w * nchunk + chunk) * 64 + j] = red[0][0];
+      if (partial2) partial2[((int64_t)w * nchunk + chunk) * 64 + j] = red[1][0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_colnorm_final(int k, int nchunk, const double* partial, double* sigma,
+                                uint32_t* status) {
+  const int w = blockIdx.x;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double s = 0;
+    for (int c = 0; c < nchunk; c++) s += partial[((int64_t)w * nchunk + c) * 64 + j];
+    s = sqrt(s);
+    if (!isfinite(s)) latch(status, ST_NONFINITE);
+    sigma[(int64_t)w * k + j] = s;
+  }
+}
+
+__global__ void k_scale_cols(int64_t n, int k, const double2* W, const double* sigma, double2* U) {
+  int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
+  int j = blockIdx.y, w = blockIdx.z;
+  if (r >= n) return;
+  double s = sigma[(int64_t)w * k + j];
+  double inv = s > 0 ? 1.0 / s : 0.0;
+  int64_t off = ((int64_t)w * k + j) * n + r;
+  double2 v = W[off];
+  U[off] = make_double2(v.x * inv, v.y * inv);
+}
+
+hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, double* sigma,
+                                double* U, SmallWs& ws, uint32_t* status, hipStream_t s) {
+  int nc = nchunks(n);
+  if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
+  double* part = ws.partial;
+  hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
+                     (double2*)W, (const double2*)nullptr, nc, part, (double*)nullptr);
+  hipLaunchKernelGGL(k_colnorm_final, dim3(n_omega), dim3(64), 0, s, k, nc, part, sigma, status);
+  if (U)
+    hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, k, n_omega), dim3(256), 0, s,
+                       (int64_t)n, k, (const double2*)W, (const double*)sigma, (double2*)U);
+  return hipGetLastError();
+}
+
+// After X += D: a column has converged when ||D_j|| <= tol ||X_j||.  Counts
+// unconverged columns into *fail_count (reset by the caller per solve).
+__global__ void k_refine_check(int k, int nchunk, const double* px, const double* pd, double tol,
+                               uint32_t* fail_count, uint32_t* status) {
+  const int w = blockIdx.x;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double sx = 0, sd = 0;
+    for (int c = 0; c < nchunk; c++) {
+      sx += px[((int64_t)w * nchunk + c) * 64 + j];
+      sd += pd[((int64_t)w * nchunk + c) * 64 + j];
+    }
+    if (!isfinite(sx) || !isfinite(sd)) latch(status, ST_NONFINITE);
+    if (!(sqrt(sd) <= tol * sqrt(sx))) atomicAdd(fail_count, 1u);
+  }
+}
+
+hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D, double tol,
+                                SmallWs& ws, uint32_t* status, uint32_t* fail_count,
+                                hipStream_t s) {
+  int nc = nchunks(n);
+  if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
+  double* px = ws.partial;
+  double* pd = ws.partial + (size_t)n_omega * nc * 64;
+  hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
+                     (double2*)X, (const double2*)D, nc, px, pd);
+  hipLaunchKernelGGL(k_refine_check, dim3(n_omega), dim3(64), 0, s, k, nc, px, pd, tol,
+                     fail_count, status);
+  return hipGetLastError();
+}
+
+}  // namespace rr

@@ -1,0 +1,73 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/rr.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1902_01458_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "rr.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rr_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for must in ("rr_factor", "rr_sketch_solve", "rr_adjoint_solve", "rr_gains", "rr_grad"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+    for name in _lib.EXPORTS:
+        assert hasattr(L, name), name
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    one = (ctypes.c_double * 1)(1.0)
+    # NULL problem
+    assert L.rr_factor(None, one, None, 1, 4, 0, None, None, ctypes.byref(h)) == 1
+    assert b"NULL" in L.rr_last_error()
+    # bad sizes
+    p = _lib.Problem(0, 4, None, None, None, 0, 1, 0, 1, 0.01)
+    assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 0, None, None, ctypes.byref(h)) == 1
+    p = _lib.Problem(4, 4, 1, None, None, 0, 1, 0, 1, 0.01)
+    assert L.rr_factor(ctypes.byref(p), one, None, 0, 4, 0, None, None, ctypes.byref(h)) == 1
+    assert L.rr_factor(ctypes.byref(p), one, None, 1, 0, 0, None, None, ctypes.byref(h)) == 1
+    assert L.rr_factor(ctypes.byref(p), one, None, 1, 33, 0, None, None, ctypes.byref(h)) == 1
+    assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 7, None, None, ctypes.byref(h)) == 1
+    nan = (ctypes.c_double * 1)(float("nan"))
+    assert L.rr_factor(ctypes.byref(p), nan, None, 1, 4, 0, None, None, ctypes.byref(h)) == 1
+    bad_tile = _lib.Tuning(48, 0, 0, 0.0)
+    assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 0, ctypes.byref(bad_tile), None,
+                       ctypes.byref(h)) == 1
+    assert not h
+    assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 0, None, None, None) == 1
+    # calls on a NULL handle
+    assert L.rr_sketch_solve(None, 4, 0, 0, None, None) == 1
+    assert L.rr_adjoint_solve(None, 4, None, None, None) == 1
+    assert L.rr_gains(None, 4, None, None, 0, None, None, None, None, None) == 1
+    assert L.rr_grad(None, None, None, None, 0, None, None, None, None) == 1
+    assert L.rr_check(None, None) == 1
+    assert L.rr_refine_count(None) == 0
+    assert L.rr_bytes(None) == 0
+    L.rr_factors_free(None)
+    assert L.rr_burgers_coeffs(0, 3, None, 0, 1, 0, 1, 0.1, None, None, None) == 1
+    assert L.rr_philox_raw(None, 4, 0, 0, 0, 0, None) == 1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "librr.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()
