@@ -61,7 +61,7 @@ rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
 }
 
 void free_all(rr_factors* f) {
-  void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->flags, f->ctrl, f->theta,
+  void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->flags, f->ctrl, f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
                 f->small.Rinv, f->small.W, f->small.Ut, f->grad_partial};
   for (void* p : ps)
@@ -89,14 +89,15 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
                     double* X, hipStream_t s) {
   const bool mixed = f->prec == RR_MIXED;
   RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
-                      f->flags, ticket_word(f), st_word(f), f->grid, s));
+                      f->xs, f->flags, ticket_word(f), st_word(f), f->solve_grid, s));
   if (!mixed) return RR_OK;
   double* res = f->work3;
   for (int it = 0; it < f->refine_iters; it++) {
     // res = Bm - M X in FP64 from the stencil, then res <- M32^-1 res, X += res
     RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, k, adjoint, X, Bm, bstride, res, s));
     RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
-                        (int64_t)k * f->n, res, f->flags, ticket_word(f), st_word(f), f->grid, s));
+                        (int64_t)k * f->n, res, f->xs, f->flags, ticket_word(f), st_word(f),
+                        f->solve_grid, s));
     RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
     RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, f->refine_tol, f->small, st_word(f),
                                 fail_word(f), s));
@@ -191,6 +192,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->geom.B = (b + T - 1) / T;
   f->geom.NB = (f->n + T - 1) / T;
   f->grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
+  f->solve_grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
   f->refine_iters = tune ? (tune->refine_iters ? tune->refine_iters : 3) : 3;
   f->refine_tol = tune && tune->refine_tol > 0 ? tune->refine_tol : 1e-10;
   f->omega_host.resize(2 * n_omega);
@@ -217,6 +219,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   if (p->U) ALLOC(f->U, (size_t)(p->nx + 2) * (p->ny + 2) * sizeof(double));
   ALLOC(f->omega, 2 * n_omega * sizeof(double));
   ALLOC(f->tiles, f->tile_bytes);
+  ALLOC(f->xs, (size_t)n_omega * f->geom.NB * T * solve_np(k_max) * 2 * sizeof(double));
   ALLOC(f->flags, nflags * sizeof(int));
   f->flag_count = nflags;
   ALLOC(f->ctrl, 64 * sizeof(uint32_t));

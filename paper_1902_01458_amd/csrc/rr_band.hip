@@ -1,4 +1,4 @@
-// Band LU of M(omega) = i omega I - L and multi-RHS solves with it, on MFMA.
+// Band LU of M(omega) = i omega I - L on MFMA (the solves are in rr_solve.hip).
 //
 // The paper factors the shifted operator once and reuses the LU in the three
 // linear solves of Algorithm 1 (Section 3.1).  Here the band (kl = ku = b =
@@ -14,7 +14,7 @@
 // L_mm^-1 (strictly lower, unit diagonal implied)], so the solves and the
 // off-diagonal finalisations are GEMMs too.
 //
-// Scheduling: one persistent launch per factorisation (or per solve).  Work
+// Scheduling: one persistent launch per factorisation.  Work
 // is handed out by a global ticket counter in a dependency-respecting order
 // (every task only waits on tasks with smaller tickets), so the launch cannot
 // deadlock whatever the residency; dependencies are per-tile flags published
@@ -425,139 +425,6 @@ hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omeg
   } else {
     if (g.T == 64) return launch_factor_t<double, 64>(P, grid, s);
     if (g.T == 32) return launch_factor_t<double, 32>(P, grid, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-// ---------------------------------------------------------------------------
-// The solves
-// ---------------------------------------------------------------------------
-struct SolveParams {
-  BandGeom g;
-  int64_t n;
-  int n_omega, k;
-  int adjoint;
-  const void* tiles;
-  const double2* Bm;
-  int64_t bstride;
-  double2* X;
-  int* flags;  // n_omega * NB: 1 = first sweep done, 2 = final
-  uint32_t* ticket;
-  uint32_t* status;
-  int64_t total;  // n_omega * 2 * NB
-};
-
-template <typename R, int T, int NP>
-__global__ __launch_bounds__(kThreads) void k_solve(SolveParams P) {
-  extern __shared__ __align__(16) char smem_raw[];
-  cplx<R>* lds = reinterpret_cast<cplx<R>*>(smem_raw);
-  __shared__ uint32_t s_ticket;
-  typedef Acc<R, T / 16, NP / 16> A;
-  const int B = P.g.B, NB = P.g.NB, W = 2 * B + 1;
-  A acc;
-  for (;;) {
-    const int64_t ticket = wg_ticket(P.ticket, &s_ticket);
-    if (ticket >= P.total) break;
-    const int w = (int)(ticket % P.n_omega);
-    const int64_t task = ticket / P.n_omega;
-    const bool second = task >= NB;              // backward sweep
-    const int s = second ? (int)(2 * NB - 1 - task) : (int)task;
-    const int64_t ld = P.n;
-    const double2* Bw = P.Bm + (int64_t)w * P.bstride;
-    double2* Xw = P.X + (int64_t)w * P.k * P.n;
-    int* fl = P.flags + (int64_t)w * NB;
-    const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)w * NB * W * (T * T);
-    auto tile = [&](int r, int t) { return tw + ((int64_t)r * W + (t - r + B)) * (T * T); };
-    const int64_t row0 = (int64_t)s * T;
-    // load the right-hand side block (first sweep: Bm; second: the first sweep's result)
-    if (second) wg_wait_flag(fl + s, 1, P.status);
-    const double2* src = second ? Xw : Bw;
-#pragma unroll
-    for (int q = 0; q < A::NPW; q++) {
-      int c = A::col(q);
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        int64_t rr = row0 + A::row(q, e);
-        double2 v = make_double2(0.0, 0.0);
-        if (A::valid(q) && c < P.k && rr < P.n) v = src[(int64_t)c * ld + rr];
-        acc.re[q][e] = (R)v.x;
-        acc.im[q][e] = (R)v.y;
-      }
-    }
-    // off-diagonal contributions
-    //   forward, first sweep:  L_st  (t < s)      forward, second: U_st  (t > s)
-    //   adjoint, first sweep:  U_ts^H (t < s)     adjoint, second: L_ts^H (t > s)
-    int t0 = second ? s + 1 : max(0, s - B);
-    int t1 = second ? min(NB - 1, s + B) : s - 1;
-    for (int t = t0; t <= t1; t++) {
-      wg_wait_flag(fl + t, second ? 2 : 1, P.status);
-      const cplx<R>* Tp = P.adjoint ? tile(t, s) : tile(s, t);
-      gemm_tv<R, T, NP>(acc, lds, Tp, P.adjoint != 0, MASK_NONE, Xw, ld, (int64_t)t * T, P.n,
-                        P.k, true);
-    }
-    // diagonal block: x_s = D^-1 acc with D^-1 read from the stored inverse
-    // (forward: L^-1 then U^-1; adjoint: (U^-1)^H then (L^-1)^H)
-#pragma unroll
-    for (int q = 0; q < A::NPW; q++) {
-      int c = A::col(q);
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        int64_t rr = row0 + A::row(q, e);
-        if (A::valid(q) && c < P.k && rr < P.n)
-          Xw[(int64_t)c * ld + rr] = make_double2((double)acc.re[q][e], (double)acc.im[q][e]);
-      }
-    }
-    __threadfence_block();
-    __syncthreads();
-    acc.zero();
-    int mask = (P.adjoint ? second : !second) ? MASK_UNIT_LOWER : MASK_UPPER;
-    gemm_tv<R, T, NP>(acc, lds, tile(s, s), P.adjoint != 0, mask, Xw, ld, row0, P.n, P.k, false);
-#pragma unroll
-    for (int q = 0; q < A::NPW; q++) {
-      int c = A::col(q);
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        int64_t rr = row0 + A::row(q, e);
-        if (A::valid(q) && c < P.k && rr < P.n)
-          Xw[(int64_t)c * ld + rr] = make_double2((double)acc.re[q][e], (double)acc.im[q][e]);
-      }
-    }
-    wg_publish(fl + s, second ? 2 : 1);
-  }
-}
-
-template <typename R, int T, int NP>
-static hipError_t launch_solve_t(const SolveParams& P, int grid, hipStream_t s) {
-  size_t lds = sizeof(cplx<R>) * (size_t)KC * ((T + 1) + (NP + 1));
-  hipLaunchKernelGGL((k_solve<R, T, NP>), dim3(grid), dim3(kThreads), lds, s, P);
-  return hipGetLastError();
-}
-
-template <typename R, int T>
-static hipError_t launch_solve_np(const SolveParams& P, int grid, hipStream_t s) {
-  if (P.k <= 16) return launch_solve_t<R, T, 16>(P, grid, s);
-  if (P.k <= 32) return launch_solve_t<R, T, 32>(P, grid, s);
-  if (P.k <= 48) return launch_solve_t<R, T, 48>(P, grid, s);
-  if (P.k <= 64) return launch_solve_t<R, T, 64>(P, grid, s);
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
-                        const void* tiles, int adjoint, const double* Bm, int64_t bstride,
-                        double* X, int* flags, uint32_t* ticket, uint32_t* status, int grid,
-                        hipStream_t s) {
-  SolveParams P{g, n, n_omega, k, adjoint, tiles, (const double2*)Bm, bstride, (double2*)X,
-                flags, ticket, status, (int64_t)n_omega * 2 * g.NB};
-  hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.NB, s);
-  if (e == hipSuccess) e = launch_fill_u32(ticket, 0u, 1, s);
-  if (e != hipSuccess) return e;
-  if (grid > P.total) grid = (int)P.total;
-  if (fp32) {
-    if (g.T == 64) return launch_solve_np<float, 64>(P, grid, s);
-    if (g.T == 32) return launch_solve_np<float, 32>(P, grid, s);
-  } else {
-    if (g.T == 64) return launch_solve_np<double, 64>(P, grid, s);
-    if (g.T == 32) return launch_solve_np<double, 32>(P, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -124,10 +124,12 @@ hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omeg
                          uint32_t* status, int grid, hipStream_t s);
 // Multi-RHS solve with the band factor: X = M^-1 Bm (adjoint: M^-H Bm).
 // Bm's blocks are bstride complex elements apart (0: shared); Bm may alias X.
+// xs: workspace of n_omega * NB * T * solve_np(k) complex (FP64 size).
+int solve_np(int k);
 hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
-                        double* X, int* flags, uint32_t* ticket, uint32_t* status, int grid,
-                        hipStream_t s);
+                        double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
+                        int grid, hipStream_t s);
 
 // Small dense / tall-skinny kernels (rr_small.hip)
 struct SmallWs {   // workspace for tall-skinny reductions
@@ -170,7 +172,8 @@ struct rr_factors {
   int nx, ny, n, n_omega, k_max;
   rr_precision prec;
   rr::BandGeom geom;
-  int grid;
+  int grid;        // persistent workgroups of the factorisation
+  int solve_grid;  // persistent workgroups of a solve
   int refine_iters;
   double refine_tol;
   // private copies of the problem
@@ -187,6 +190,7 @@ struct rr_factors {
   int* flags = nullptr;               // max(factor flags, solve flags)
   size_t flag_count = 0;
   uint32_t* ctrl = nullptr;           // [0] status, [1] ticket, [2] refine fails
+  void* xs = nullptr;                 // solve sweep workspace (row-major blocks)
   // vector workspaces (n_omega*k_max*n complex each unless noted)
   double* theta = nullptr;            // k_max*n (shared by all shifts)
   double* work1 = nullptr;

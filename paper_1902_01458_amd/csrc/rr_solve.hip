@@ -1,0 +1,323 @@
+// Multi-RHS solves with the band factor of rr_band.hip (Algorithm 1 steps 2,
+// 4 and 6; Section 3.1: the one LU serves every solve).
+//
+//   forward  M X = B:    L y = b (block rows ascending),  U x = y (descending)
+//   adjoint  M^H X = B:  U^H z = b (ascending),           L^H x = z (descending)
+//
+// Block row s of either sweep needs the B neighbouring blocks of the sweep's
+// own output, x_s = D_s^-1 (b_s - sum_t T_st x_t), where D_s^-1 is the stored
+// inverse of the diagonal triangle, so every step is a complex GEMM on MFMA.
+//
+// One persistent launch per solve; tasks (shift, sweep, block row) are handed
+// out by a ticket counter in dependency order (a task only waits on smaller
+// tickets), dependencies are per-block flags.  Each wave owns one 16 x 16 block
+// of the T x NP output and reads its MFMA operands straight from memory, so
+// the off-diagonal products need no LDS and no barriers: the blocks t far from
+// s (published long ago) are consumed first and only the product with the
+// immediate predecessor waits on the critical path.  The sweep's intermediate
+// blocks live in a row-major workspace (T rows x NP columns per block) so the
+// operand loads of all waves are coalesced; they are written with agent-scope
+// stores so the release before each flag has little to write back.
+#include "rr_internal.h"
+
+namespace rr {
+
+template <typename R>
+struct Mf;
+template <>
+struct Mf<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int e) { return (l >> 4) + 4 * e; }
+};
+template <>
+struct Mf<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
+};
+
+enum { OPM_NONE = 0, OPM_UNIT_LOWER = 1, OPM_UPPER = 2 };
+
+// MFMA operand fragments of one wave for a full K = T product: k-step q
+// holds op(X)[16rb + l%16][4q + l/16] (A role) or V[4q + l/16][16cb + l%16]
+// (B role).  All loads are issued before any value is used (masks are applied
+// in a second pass, conjugation inside the MFMA sequence), so the memory
+// system overlaps them instead of paying one latency per k-step.
+template <typename R, int T>
+struct Frag {
+  cplx<R> v[T / 4];
+};
+
+// A-role fragment of X (CT: X^H instead of X) for row block rb, masked with
+// a triangular mask of X's own indices (the diagonal inverse tile).
+template <typename R, int T, bool CT>
+__device__ __forceinline__ void load_a(Frag<R, T>& f, const cplx<R>* X, int mask, int rb) {
+  const int l = threadIdx.x & 63;
+  const int i = 16 * rb + (l & 15);
+#pragma unroll
+  for (int q = 0; q < T / 4; q++) {
+    const int k = 4 * q + (l >> 4);
+    const int a = CT ? k : i, b = CT ? i : k;
+    f.v[q] = X[b * T + a];
+  }
+  if (mask != OPM_NONE) {
+#pragma unroll
+    for (int q = 0; q < T / 4; q++) {
+      const int k = 4 * q + (l >> 4);
+      const int a = CT ? k : i, b = CT ? i : k;
+      if (mask == OPM_UNIT_LOWER && a <= b) f.v[q] = cplx<R>{a == b ? (R)1 : (R)0, (R)0};
+      if (mask == OPM_UPPER && a > b) f.v[q] = cplx<R>{(R)0, (R)0};
+    }
+  }
+}
+
+template <typename R, int T, int NP>
+__device__ __forceinline__ void load_b(Frag<R, T>& f, const cplx<R>* V, int cb) {
+  const int l = threadIdx.x & 63;
+  const int j = 16 * cb + (l & 15);
+#pragma unroll
+  for (int q = 0; q < T / 4; q++) f.v[q] = V[(4 * q + (l >> 4)) * NP + j];
+}
+
+// acc (+/-)= op(A) * B over the T k-steps (complex product = 4 real MFMAs);
+// CA conjugates the A fragment (the conjugate-transposed factor of the adjoint).
+template <typename R, int T, bool CA, bool SUB>
+__device__ __forceinline__ void mma_frag(typename Mf<R>::v4& are, typename Mf<R>::v4& aim,
+                                         const Frag<R, T>& A, const Frag<R, T>& Bf) {
+#pragma unroll
+  for (int q = 0; q < T / 4; q++) {
+    const cplx<R> a = A.v[q], b = Bf.v[q];
+    const R ar = SUB ? -a.re : a.re;
+    const R ai = (SUB != CA) ? -a.im : a.im;
+    are = Mf<R>::op(ar, b.re, are);
+    are = Mf<R>::op(-ai, b.im, are);
+    aim = Mf<R>::op(ar, b.im, aim);
+    aim = Mf<R>::op(ai, b.re, aim);
+  }
+}
+
+struct Solve2Params {
+  BandGeom g;
+  int64_t n;
+  int n_omega, k;
+  int adjoint;
+  const void* tiles;
+  const double2* Bm;
+  int64_t bstride;   // complex elements between the shifts' right-hand sides
+  double2* X;        // (n_omega, k, n) result
+  void* xs;          // workspace: n_omega * NB * T * NP complex R, row-major blocks
+  int* flags;        // n_omega * NB: 1 = first sweep done, 2 = final
+  uint32_t* ticket;
+  uint32_t* status;
+  int64_t total;     // n_omega * 2 * NB
+};
+
+// Thread 0 polls flags [t0, t1] of one shift until each reaches `want`, then
+// issues one acquire fence; the barrier hands the result to every wave.
+__device__ __forceinline__ void wg_wait_range(int* fl, int t0, int t1, int want, uint32_t* status) {
+  __shared__ int dummy;
+  if (threadIdx.x == 0) {
+    bool live = !(__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT);
+    uint64_t t_start = wall_clock64();
+    uint32_t polls = 0;
+    for (int t = t0; live && t <= t1; t++) {
+      while (__hip_atomic_fetch_add(fl + t, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++polls > kWaitPolls || wall_clock64() - t_start > kWaitTicks) {
+          latch(status, ST_TIMEOUT);
+          live = false;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    dummy = 0;
+  }
+  __syncthreads();
+}
+
+// Every thread's stores have left the CU (s_waitcnt), then thread 0 writes back
+// the L2 (agent release) and sets the flag.  Barriers close the interval on
+// both sides (see wg_publish).
+__device__ __forceinline__ void wg_publish_one(int* flag, int value) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+template <typename R, int T, int NP, bool ADJ>
+__global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Params P) {
+  constexpr int NCB = NP / 16;
+  extern __shared__ __align__(16) char solve_smem[];
+  cplx<R>* blk = reinterpret_cast<cplx<R>*>(solve_smem);  // pre-diagonal block, row-major
+  __shared__ uint32_t s_ticket;
+  typedef typename Mf<R>::v4 v4;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int rb = wave / NCB, cb = wave % NCB;
+  const int B = P.g.B, NB = P.g.NB, W = 2 * B + 1;
+  for (;;) {
+    const int64_t ticket = wg_ticket(P.ticket, &s_ticket);
+    if (ticket >= P.total) break;
+    const int w = (int)(ticket % P.n_omega);
+    const int64_t task = ticket / P.n_omega;
+    const bool second = task >= NB;
+    const int s = second ? (int)(2 * NB - 1 - task) : (int)task;
+    int* fl = P.flags + (int64_t)w * NB;
+    const cplx<R>* tw =
+        reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)w * NB * W * (T * T);
+    auto tile = [&](int r, int t) { return tw + ((int64_t)r * W + (t - r + B)) * (T * T); };
+    cplx<R>* xw = reinterpret_cast<cplx<R>*>(P.xs) + (int64_t)w * NB * T * NP;
+    const int j = 16 * cb + (l & 15);  // this lane's column in the block
+    v4 are, aim;
+    // right-hand side: b_s (first sweep) or the first sweep's y_s (second)
+    if (second) {
+      wg_wait_range(fl, s, s, 1, P.status);
+      const cplx<R>* ys = xw + (int64_t)s * T * NP;
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        cplx<R> v = ys[(16 * rb + Mf<R>::row(l, e)) * NP + j];
+        are[e] = v.re;
+        aim[e] = v.im;
+      }
+    } else {
+      const double2* Bw = P.Bm + (int64_t)w * P.bstride;
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        int64_t r = (int64_t)s * T + 16 * rb + Mf<R>::row(l, e);
+        double2 v = make_double2(0.0, 0.0);
+        if (j < P.k && r < P.n) v = Bw[(int64_t)j * P.n + r];
+        are[e] = (R)v.x;
+        aim[e] = (R)v.y;
+      }
+    }
+    // off-diagonal products
+    //   forward first: L_st (t < s); forward second: U_st (t > s)
+    //   adjoint first: U_ts^H (t < s); adjoint second: L_ts^H (t > s)
+    // The operands of the two products on the critical path (the neighbour
+    // block and the diagonal inverse) are fetched before any wait: they are
+    // factor data, final before the launch.
+    const int want = second ? 2 : 1;
+    const int dir = second ? 1 : -1;
+    const int near = s + dir;
+    const bool has_near = near >= 0 && near < NB;
+    const int mask = (ADJ ? second : !second) ? OPM_UNIT_LOWER : OPM_UPPER;
+    // the diagonal inverse is prefetched too where registers allow (FP32, or
+    // the 32-wide tile); otherwise it is read after the critical product
+    constexpr bool kPreDiag = sizeof(R) == 4 || T == 32;
+    Frag<R, T> a_near, a_diag, fb;
+    if (has_near) load_a<R, T, ADJ>(a_near, ADJ ? tile(near, s) : tile(s, near), OPM_NONE, rb);
+    if (kPreDiag) load_a<R, T, ADJ>(a_diag, tile(s, s), mask, rb);
+    // far blocks (|t - s| >= 3), then the block two away, then the neighbour
+    int f0, f1;
+    if (second) { f0 = s + 3; f1 = min(NB - 1, s + B); } else { f0 = max(0, s - B); f1 = s - 3; }
+    if (f0 <= f1) {
+      wg_wait_range(fl, f0, f1, want, P.status);
+      for (int t = f0; t <= f1; t++) {
+        Frag<R, T> fa;
+        load_a<R, T, ADJ>(fa, ADJ ? tile(t, s) : tile(s, t), OPM_NONE, rb);
+        load_b<R, T, NP>(fb, xw + (int64_t)t * T * NP, cb);
+        mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
+      }
+    }
+    const int mid = s + 2 * dir;
+    if (B >= 2 && mid >= 0 && mid < NB) {
+      wg_wait_range(fl, mid, mid, want, P.status);
+      Frag<R, T> fa;
+      load_a<R, T, ADJ>(fa, ADJ ? tile(mid, s) : tile(s, mid), OPM_NONE, rb);
+      load_b<R, T, NP>(fb, xw + (int64_t)mid * T * NP, cb);
+      mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
+    }
+    if (has_near) {
+      wg_wait_range(fl, near, near, want, P.status);
+      load_b<R, T, NP>(fb, xw + (int64_t)near * T * NP, cb);
+      mma_frag<R, T, ADJ, true>(are, aim, a_near, fb);
+    }
+    // diagonal block: x_s = D_s^-1 acc  (forward: L^-1 then U^-1; adjoint:
+    // (U^-1)^H then (L^-1)^H, all read from the stored inverse tile)
+#pragma unroll
+    for (int e = 0; e < 4; e++) blk[(16 * rb + Mf<R>::row(l, e)) * NP + j] = cplx<R>{are[e], aim[e]};
+    __syncthreads();
+    for (int e = 0; e < 4; e++) { are[e] = 0; aim[e] = 0; }
+    if (!kPreDiag) load_a<R, T, ADJ>(a_diag, tile(s, s), mask, rb);
+    load_b<R, T, NP>(fb, blk, cb);
+    mma_frag<R, T, ADJ, false>(are, aim, a_diag, fb);
+    cplx<R>* xs = xw + (int64_t)s * T * NP;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      cplx<R>* d = xs + (16 * rb + Mf<R>::row(l, e)) * NP + j;
+      __hip_atomic_store(&d->re, are[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&d->im, aim[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (second) {
+      double2* Xw = P.X + (int64_t)w * P.k * P.n;
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        int64_t r = (int64_t)s * T + 16 * rb + Mf<R>::row(l, e);
+        if (j < P.k && r < P.n) Xw[(int64_t)j * P.n + r] = make_double2((double)are[e], (double)aim[e]);
+      }
+    }
+    wg_publish_one(fl + s, want);
+  }
+}
+
+template <typename R, int T, int NP, bool ADJ>
+static hipError_t launch_a(const Solve2Params& P, int grid, hipStream_t s) {
+  size_t lds = sizeof(cplx<R>) * (size_t)T * NP;
+  hipError_t e = hipFuncSetAttribute((const void*)k_solve2<R, T, NP, ADJ>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve2<R, T, NP, ADJ>), dim3(grid), dim3(64 * (T / 16) * (NP / 16)), lds,
+                     s, P);
+  return hipGetLastError();
+}
+
+template <typename R, int T, int NP>
+static hipError_t launch_t(const Solve2Params& P, int grid, hipStream_t s) {
+  return P.adjoint ? launch_a<R, T, NP, true>(P, grid, s) : launch_a<R, T, NP, false>(P, grid, s);
+}
+
+template <typename R, int T>
+static hipError_t launch_np(const Solve2Params& P, int NP, int grid, hipStream_t s) {
+  switch (NP) {
+    case 16: return launch_t<R, T, 16>(P, grid, s);
+    case 32: return launch_t<R, T, 32>(P, grid, s);
+    case 48: return launch_t<R, T, 48>(P, grid, s);
+    case 64: return launch_t<R, T, 64>(P, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int solve_np(int k) { return ((k + 15) / 16) * 16; }
+
+hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
+                        const void* tiles, int adjoint, const double* Bm, int64_t bstride,
+                        double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
+                        int grid, hipStream_t s) {
+  int NP = solve_np(k);
+  if (NP > 64 || (g.T == 64 && NP > 64) || (g.T * NP > 64 * 64)) return hipErrorInvalidValue;
+  Solve2Params P{g, n, n_omega, k, adjoint, tiles, (const double2*)Bm, bstride, (double2*)X,
+                 xs, flags, ticket, status, (int64_t)n_omega * 2 * g.NB};
+  hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.NB, s);
+  if (e == hipSuccess) e = launch_fill_u32(ticket, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  if (grid > P.total) grid = (int)P.total;
+  if (fp32) {
+    if (g.T == 64) return launch_np<float, 64>(P, NP, grid, s);
+    if (g.T == 32) return launch_np<float, 32>(P, NP, grid, s);
+  } else {
+    if (g.T == 64) return launch_np<double, 64>(P, NP, grid, s);
+    if (g.T == 32) return launch_np<double, 32>(P, NP, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rr
