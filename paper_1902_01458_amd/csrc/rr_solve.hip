@@ -18,28 +18,9 @@
 // blocks live in a row-major workspace (T rows x NP columns per block) so the
 // operand loads of all waves are coalesced; they are written with agent-scope
 // stores so the release before each flag has little to write back.
-#include "rr_internal.h"
+#include "rr_mfma.h"
 
 namespace rr {
-
-template <typename R>
-struct Mf;
-template <>
-struct Mf<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int e) { return (l >> 4) + 4 * e; }
-};
-template <>
-struct Mf<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
-};
 
 enum { OPM_NONE = 0, OPM_UNIT_LOWER = 1, OPM_UPPER = 2 };
 
@@ -54,16 +35,18 @@ struct Frag {
 };
 
 // A-role fragment of X (CT: X^H instead of X) for row block rb, masked with
-// a triangular mask of X's own indices (the diagonal inverse tile).
+// a triangular mask of X's own indices (the diagonal inverse tile).  X is
+// stored column-major, or row-major when xt (the factor's U tiles).
 template <typename R, int T, bool CT>
-__device__ __forceinline__ void load_a(Frag<R, T>& f, const cplx<R>* X, int mask, int rb) {
+__device__ __forceinline__ void load_a(Frag<R, T>& f, const cplx<R>* X, int mask, int rb,
+                                       bool xt = false) {
   const int l = threadIdx.x & 63;
   const int i = 16 * rb + (l & 15);
 #pragma unroll
   for (int q = 0; q < T / 4; q++) {
     const int k = 4 * q + (l >> 4);
     const int a = CT ? k : i, b = CT ? i : k;
-    f.v[q] = X[b * T + a];
+    f.v[q] = X[xt ? a * T + b : b * T + a];
   }
   if (mask != OPM_NONE) {
 #pragma unroll
@@ -90,15 +73,7 @@ template <typename R, int T, bool CA, bool SUB>
 __device__ __forceinline__ void mma_frag(typename Mf<R>::v4& are, typename Mf<R>::v4& aim,
                                          const Frag<R, T>& A, const Frag<R, T>& Bf) {
 #pragma unroll
-  for (int q = 0; q < T / 4; q++) {
-    const cplx<R> a = A.v[q], b = Bf.v[q];
-    const R ar = SUB ? -a.re : a.re;
-    const R ai = (SUB != CA) ? -a.im : a.im;
-    are = Mf<R>::op(ar, b.re, are);
-    are = Mf<R>::op(-ai, b.im, are);
-    aim = Mf<R>::op(ar, b.im, aim);
-    aim = Mf<R>::op(ai, b.re, aim);
-  }
+  for (int q = 0; q < T / 4; q++) cmfma<R, CA, SUB>(are, aim, A.v[q], Bf.v[q]);
 }
 
 struct Solve2Params {
@@ -210,11 +185,12 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     const int near = s + dir;
     const bool has_near = near >= 0 && near < NB;
     const int mask = (ADJ ? second : !second) ? OPM_UNIT_LOWER : OPM_UPPER;
+    const bool ut = ADJ != second;  // off-diagonal tiles of this sweep are U tiles (row-major)
     // the diagonal inverse is prefetched too where registers allow (FP32, or
     // the 32-wide tile); otherwise it is read after the critical product
     constexpr bool kPreDiag = sizeof(R) == 4 || T == 32;
     Frag<R, T> a_near, a_diag, fb;
-    if (has_near) load_a<R, T, ADJ>(a_near, ADJ ? tile(near, s) : tile(s, near), OPM_NONE, rb);
+    if (has_near) load_a<R, T, ADJ>(a_near, ADJ ? tile(near, s) : tile(s, near), OPM_NONE, rb, ut);
     if (kPreDiag) load_a<R, T, ADJ>(a_diag, tile(s, s), mask, rb);
     // far blocks (|t - s| >= 3), then the block two away, then the neighbour
     int f0, f1;
@@ -223,7 +199,7 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
       wg_wait_range(fl, f0, f1, want, P.status);
       for (int t = f0; t <= f1; t++) {
         Frag<R, T> fa;
-        load_a<R, T, ADJ>(fa, ADJ ? tile(t, s) : tile(s, t), OPM_NONE, rb);
+        load_a<R, T, ADJ>(fa, ADJ ? tile(t, s) : tile(s, t), OPM_NONE, rb, ut);
         load_b<R, T, NP>(fb, xw + (int64_t)t * T * NP, cb);
         mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
       }
@@ -232,7 +208,7 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     if (B >= 2 && mid >= 0 && mid < NB) {
       wg_wait_range(fl, mid, mid, want, P.status);
       Frag<R, T> fa;
-      load_a<R, T, ADJ>(fa, ADJ ? tile(mid, s) : tile(s, mid), OPM_NONE, rb);
+      load_a<R, T, ADJ>(fa, ADJ ? tile(mid, s) : tile(s, mid), OPM_NONE, rb, ut);
       load_b<R, T, NP>(fb, xw + (int64_t)mid * T * NP, cb);
       mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
     }

@@ -76,6 +76,8 @@ SOLVE_CASES = [  # (nx, ny, tile, k): ragged n and b, several tiles per half-ban
     (13, 20, 64, 17),
     (24, 40, 32, 5),
     (9, 48, 64, 20),
+    (16, 96, 32, 12),   # B = 6 tiles per half-band: early/final task split
+    (12, 100, 64, 32),  # B = 4 at the 64 tile, ragged n, k = 32
 ]
 
 
