@@ -110,10 +110,17 @@ typedef struct {
 typedef struct {
   int32_t tile;          /* band tile edge T: 32 or 64 (default 64)             */
   int32_t grid;          /* persistent workgroups per launch; 0 = 2 per CU      */
-  int32_t refine_iters;  /* mixed only: fixed correction count per solve
-                            (default 3); convergence is still checked           */
-  double  refine_tol;    /* mixed only: per-column ||d_j|| <= tol*||x_j||
+  int32_t refine_iters;  /* mixed only: most corrections per solve (default 6,
+                            at most 16).  The launches are fixed (graph-safe)
+                            but skip their work on the device once every
+                            column of every shift has converged               */
+  double  refine_tol;    /* mixed only: a column has converged when its last
+                            correction d_j has ||d_j|| <= tol*||x_j||, for the
+                            projection (step 4) and recovery (step 6) solves
                             (default 1e-10)                                     */
+  double  refine_tol_sketch; /* mixed only: the same test for the sketch and
+                            subspace-iteration solves, which only fix the
+                            basis Q (default 1e-8)                              */
 } rr_tuning;
 
 typedef struct rr_factors rr_factors;
@@ -196,8 +203,8 @@ rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const d
  * latched in the handle since the last check; RR_OK if none. */
 rr_status rr_check(rr_factors* f, void* stream);
 
-/* Number of correction steps the last mixed-precision solves needed at most
- * (0 for FP64), read after rr_check. */
+/* Largest number of correction steps any mixed-precision solve needed since
+ * the previous rr_check (0 for FP64); valid after rr_check. */
 int32_t rr_refine_count(rr_factors* f);
 
 /* Device bytes held by the handle. */

@@ -35,7 +35,8 @@ class Problem(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("refine_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+                ("refine_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("refine_tol_sketch", ctypes.c_double)]
 
 
 _lib = None

@@ -107,7 +107,7 @@ class Factors:
 
     def __init__(self, prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32,
                  tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
-                 stream=None):
+                 refine_tol_sketch: float = 0.0, stream=None):
         om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
         self.prob = prob
         self.omegas = om
@@ -118,7 +118,7 @@ class Factors:
         self._h = ctypes.c_void_p()
         re = np.ascontiguousarray(om.real)
         im = np.ascontiguousarray(om.imag)
-        tune = _lib.Tuning(tile, grid, refine_iters, refine_tol)
+        tune = _lib.Tuning(tile, grid, refine_iters, refine_tol, refine_tol_sketch)
         ps = prob.c_struct()
         check(lib().rr_factor(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
                               im.ctypes.data_as(ctypes.c_void_p), self.n_omega, k_max,

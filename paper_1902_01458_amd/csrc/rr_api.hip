@@ -73,38 +73,49 @@ OpDesc opdesc(const rr_factors* f) { return OpDesc{f->nx, f->ny, f->n, f->coef};
 uint32_t* st_word(rr_factors* f) { return f->ctrl; }
 uint32_t* ticket_word(rr_factors* f) { return f->ctrl + 1; }
 uint32_t* fail_word(rr_factors* f) { return f->ctrl + 2; }
+uint32_t* conv_word(rr_factors* f) { return f->ctrl + 3; }
 // ctrl[4 + it]: unconverged columns after correction it (mixed solves)
 constexpr int kMaxRefine = 16;
 
-__global__ void k_latch_if_nonzero(const uint32_t* count, uint32_t* status, uint32_t bit) {
-  if (threadIdx.x == 0 && *count) atomicOr(status, bit);
+// After correction `it`: record the unconverged-column count and mark the
+// solve converged when it is zero (later corrections then skip their work).
+__global__ void k_refine_step(const uint32_t* fail, uint32_t* slot, uint32_t* conv) {
+  if (threadIdx.x == 0) {
+    uint32_t nf = *fail;
+    atomicMax(slot, nf);
+    if (nf == 0) *conv = 1u;
+  }
 }
-__global__ void k_record_max(const uint32_t* count, uint32_t* slot) {
-  if (threadIdx.x == 0) atomicMax(slot, *count);
+__global__ void k_latch_unless(const uint32_t* conv, uint32_t* status, uint32_t bit) {
+  if (threadIdx.x == 0 && !*conv) atomicOr(status, bit);
 }
 
 // X = M^-1 Bm (or M^-H): one FP64 band solve, or FP32 solves with FP64
-// residual refinement.  Bm's blocks are bstride apart (0 = shared by all shifts).
+// residual refinement to `tol`.  Bm's blocks are bstride apart (0 = shared by
+// all shifts).  The mixed loop has a fixed number of launches; once every
+// column of every shift has converged the remaining ones return at once.
 rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t bstride,
-                    double* X, hipStream_t s) {
+                    double* X, double tol, hipStream_t s) {
   const bool mixed = f->prec == RR_MIXED;
   RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
                       f->xs, f->flags, ticket_word(f), st_word(f), f->solve_grid, s));
   if (!mixed) return RR_OK;
   double* res = f->work3;
+  RR_HIP(launch_fill_u32(conv_word(f), 0u, 1, s));
   for (int it = 0; it < f->refine_iters; it++) {
     // res = Bm - M X in FP64 from the stencil, then res <- M32^-1 res, X += res
-    RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, k, adjoint, X, Bm, bstride, res, s));
+    RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, k, adjoint, X, Bm, bstride, res, s,
+                        conv_word(f)));
     RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
                         (int64_t)k * f->n, res, f->xs, f->flags, ticket_word(f), st_word(f),
-                        f->solve_grid, s));
+                        f->solve_grid, s, conv_word(f)));
     RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
-    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, f->refine_tol, f->small, st_word(f),
-                                fail_word(f), s));
-    hipLaunchKernelGGL(k_record_max, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
-                       f->ctrl + 4 + it);
+    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, f->small, st_word(f),
+                                fail_word(f), s, conv_word(f)));
+    hipLaunchKernelGGL(k_refine_step, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
+                       f->ctrl + 4 + it, conv_word(f));
   }
-  hipLaunchKernelGGL(k_latch_if_nonzero, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
+  hipLaunchKernelGGL(k_latch_unless, dim3(1), dim3(64), 0, s, (const uint32_t*)conv_word(f),
                      st_word(f), (uint32_t)ST_NOT_CONVERGED);
   RR_HIP(hipGetLastError());
   return RR_OK;
@@ -193,8 +204,9 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->geom.NB = (f->n + T - 1) / T;
   f->grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
   f->solve_grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
-  f->refine_iters = tune ? (tune->refine_iters ? tune->refine_iters : 3) : 3;
+  f->refine_iters = tune && tune->refine_iters ? tune->refine_iters : 6;
   f->refine_tol = tune && tune->refine_tol > 0 ? tune->refine_tol : 1e-10;
+  f->refine_tol_sketch = tune && tune->refine_tol_sketch > 0 ? tune->refine_tol_sketch : 1e-8;
   f->omega_host.resize(2 * n_omega);
   for (int i = 0; i < n_omega; i++) {
     f->omega_host[2 * i] = omega_re[i];
@@ -300,12 +312,13 @@ rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power
   const int64_t blk = (int64_t)k * f->n;
   RR_HIP(launch_fill_u32(f->ctrl + 4, 0u, kMaxRefine, s));
   RR_HIP(launch_sketch(opdesc(f), f->phi, k, seed, f->theta, s));                   // step 1
-  if ((st = solve_any(f, k, 0, f->theta, 0, Q, s)) != RR_OK) return st;             // step 2
+  const double ts = f->refine_tol_sketch;
+  if ((st = solve_any(f, k, 0, f->theta, 0, Q, ts, s)) != RR_OK) return st;         // step 2
   RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));       // step 3
   for (int it = 0; it < power_iters; it++) {                                        // 2.2.1
-    if ((st = solve_any(f, k, 1, Q, blk, f->work1, s)) != RR_OK) return st;
+    if ((st = solve_any(f, k, 1, Q, blk, f->work1, ts, s)) != RR_OK) return st;
     RR_HIP(launch_cholqr2(f->n, f->n_omega, k, f->work1, f->work1, f->small, st_word(f), s));
-    if ((st = solve_any(f, k, 0, f->work1, blk, Q, s)) != RR_OK) return st;
+    if ((st = solve_any(f, k, 0, f->work1, blk, Q, ts, s)) != RR_OK) return st;
     RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));
   }
   return RR_OK;
@@ -316,7 +329,8 @@ rr_status rr_adjoint_solve(rr_factors* f, int32_t k, const double* Q, double* Z,
   if (st != RR_OK) return st;
   if (!Q || !Z) return fail(RR_ERR_INVALID, "NULL pointer");
   if (Q == Z && f->prec == RR_MIXED) return fail(RR_ERR_INVALID, "Z may not alias Q (mixed)");
-  return solve_any(f, k, 1, Q, (int64_t)k * f->n, Z, (hipStream_t)stream);        // step 4
+  return solve_any(f, k, 1, Q, (int64_t)k * f->n, Z, f->refine_tol,                // step 4
+                   (hipStream_t)stream);
 }
 
 rr_status rr_solve(rr_factors* f, int32_t k, const double* Bm, double* X, void* stream) {
@@ -324,7 +338,7 @@ rr_status rr_solve(rr_factors* f, int32_t k, const double* Bm, double* X, void* 
   if (st != RR_OK) return st;
   if (!Bm || !X) return fail(RR_ERR_INVALID, "NULL pointer");
   if (Bm == X) return fail(RR_ERR_INVALID, "X may not alias Bm");
-  return solve_any(f, k, 0, Bm, (int64_t)k * f->n, X, (hipStream_t)stream);
+  return solve_any(f, k, 0, Bm, (int64_t)k * f->n, X, f->refine_tol, (hipStream_t)stream);
 }
 
 rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z, rr_response mode,
@@ -345,7 +359,7 @@ rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z, r
   if (mode == RR_RESP_AV) {
     // steps 6-9: W = M^-1 V, sigma_j = ||W_j||, u_j = W_j / sigma_j
     double* W = Uresp ? Uresp : f->work2;
-    if ((st = solve_any(f, k, 0, V, (int64_t)k * f->n, W, s)) != RR_OK) return st;
+    if ((st = solve_any(f, k, 0, V, (int64_t)k * f->n, W, f->refine_tol, s)) != RR_OK) return st;
     RR_HIP(launch_colnorm_scale(f->n, f->n_omega, k, W, sigma_AV, Uresp, f->small, st_word(f), s));
   }
   return RR_OK;
@@ -391,7 +405,11 @@ rr_status rr_check(rr_factors* f, void* stream) {
   if (w & ST_SINGULAR) return fail(RR_ERR_SINGULAR, "zero or non-finite pivot in the band LU");
   if (w & ST_NONFINITE) return fail(RR_ERR_NONFINITE, "non-finite values in the results");
   if (w & ST_BREAKDOWN) return fail(RR_ERR_BREAKDOWN, "Gram matrix not positive definite");
-  if (w & ST_NOT_CONVERGED) return fail(RR_ERR_NOT_CONVERGED, "refinement did not converge");
+  if (w & ST_NOT_CONVERGED) {
+    std::string m = "refinement did not converge (most unconverged columns after each correction:";
+    for (int it = 0; it < f->refine_iters; it++) m += " " + std::to_string(ctrl[4 + it]);
+    return fail(RR_ERR_NOT_CONVERGED, m + ")");
+  }
   return RR_OK;
 }
 

@@ -27,6 +27,8 @@
 // so the chain from one diagonal block to the next carries one update GEMM,
 // one finalisation GEMM and one T x T LU.  The tile of M itself is generated
 // from the stencil in registers: the band is never read before it is final.
+// Every tile store is device-coherent (st_coherent): a tile is written twice
+// per launch, from different XCDs in general, and read from others.
 #include "rr_mfma.h"
 
 namespace rr {
@@ -247,7 +249,6 @@ __device__ __forceinline__ int* flag_ptr(const FactorParams& P, int w, int r, in
 // (r, s) and (s, t), s in [s0, s1] (to 2 = final), then one acquire fence.
 __device__ __forceinline__ void wait_inputs(const FactorParams& P, int w, int r, int t, int s0,
                                             int s1, int* extra, int extra_want) {
-  __shared__ int dummy;
   if (threadIdx.x == 0) {
     bool live =
         !(__hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT);
@@ -274,7 +275,6 @@ __device__ __forceinline__ void wait_inputs(const FactorParams& P, int w, int r,
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    dummy = 0;
   }
   __syncthreads();
 }
@@ -316,7 +316,8 @@ __device__ __forceinline__ void acc_to_tile(const Acc2<R>& acc, cplx<R>* X, bool
     const int c = 32 * cp + 16 * b + (l & 15);
 #pragma unroll
     for (int e = 0; e < 4; e++)
-      X[tix(16 * rb + Mf<R>::row(l, e), c, T, rowmajor)] = cplx<R>{acc.re[b][e], acc.im[b][e]};
+      st_coherent(&X[tix(16 * rb + Mf<R>::row(l, e), c, T, rowmajor)],
+                  cplx<R>{acc.re[b][e], acc.im[b][e]});
   }
 }
 
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       __syncthreads();
       lu_inv_tile<R, T, G::NT>(lds, G::LDT, tmpL, tmpU, P.status);
       for (int idx = threadIdx.x; idx < T * T; idx += G::NT)
-        X[idx] = lds[(idx / T) * G::LDT + idx % T];
+        st_coherent(&X[idx], lds[(idx / T) * G::LDT + idx % T]);
     } else if (r > t) {
       // L_rm = A_rm U_mm^-1: A from LDS (column-major), U^-1 = upper part of D
       acc_to_lds<R, T>(acc, lds, false, rb, cp);

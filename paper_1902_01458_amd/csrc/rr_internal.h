@@ -35,56 +35,37 @@ __device__ __forceinline__ void latch(uint32_t* status, uint32_t bit) {
   atomicOr(status, bit);
 }
 
+// Store of data that another workgroup of the same launch reads after a flag
+// handshake (tiles of the factorisation, blocks of the solves).  gfx950 has
+// one L2 per XCD.  With ordinary write-back stores, an agent-scope release
+// before the flag and an acquire after it did not reliably hand a band tile
+// to readers on other XCDs (nor did system-scope fences): at n = 262144 with
+// 16 shifts about half of the refactorisations gave a wrong LU.  A relaxed
+// agent-scope atomic store is device-coherent (sc1, written through), and the
+// s_waitcnt before the release covers its completion; with every handed-over
+// tile stored this way none of 48 factorisations was wrong.  Readers keep
+// ordinary loads after their acquire.
+__device__ __forceinline__ void st_coherent(cplx<float>* p, cplx<float> v) {
+  uint64_t bits = (uint64_t)__float_as_uint(v.re) | ((uint64_t)__float_as_uint(v.im) << 32);
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bits, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(cplx<double>* p, cplx<double> v) {
+  __hip_atomic_store(&p->re, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->im, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Hard bound on polls of one wait, independent of the clock (a poll is one
 // device-coherent atomic plus a short sleep, i.e. at least ~1 us).
 constexpr uint32_t kWaitPolls = 1u << 25;
 
-// Agent-scope wait on a flag word set by another workgroup.  Thread 0 polls
-// with a relaxed atomic read-modify-write (performed device-coherently, so it
-// needs no cache invalidation per poll), then issues one acquire fence; the
-// workgroup barrier afterwards orders every thread's later loads.  Returns
-// false (and latches ST_TIMEOUT) if the wait bound is exceeded or a timeout was
-// already latched, so a broken dependency drains instead of hanging.
-__device__ __forceinline__ bool wg_wait_flag(int* flag, int want, uint32_t* status) {
-  __shared__ int ok;
-  if (threadIdx.x == 0) {
-    int good = 1;
-    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT) {
-      good = 0;
-    } else {
-      uint64_t t0 = wall_clock64();
-      uint32_t polls = 0;
-      while (__hip_atomic_fetch_add(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++polls > kWaitPolls || wall_clock64() - t0 > kWaitTicks) {
-          latch(status, ST_TIMEOUT);
-          good = 0;
-          break;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    ok = good;
-  }
-  __syncthreads();
-  return ok != 0;
-}
-
-// Make this workgroup's global stores visible device-wide, then publish a flag.
-// The trailing barrier keeps thread 0's flag store and its next ticket fetch
-// (wg_ticket) in separate barrier intervals: with both guarded by the same
-// "thread 0" test and nothing convergent between them, the compiler may send
-// the other threads straight from here to the ticket barrier, which splits the
-// persistent loop so that only thread 0 ever leaves it to take a new ticket.
-__device__ __forceinline__ void wg_publish(int* flag, int value) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-}
-
 // Next ticket of a persistent launch, the same value in every thread.  The
 // leading barrier closes the previous task (its readers of *slot are done).
+// Every flag publish before it ends with a barrier too: with the flag store
+// and the ticket fetch both guarded by "thread 0" and nothing convergent in
+// between, the compiler may otherwise send the other threads straight to the
+// ticket barrier, splitting the persistent loop so that only thread 0 ever
+// leaves it to take a new ticket.
 __device__ __forceinline__ int64_t wg_ticket(uint32_t* counter, uint32_t* slot) {
   __syncthreads();
   if (threadIdx.x == 0) *slot = atomicAdd(counter, 1u);
@@ -112,9 +93,10 @@ hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, dou
                                  double nu, double* coef, double* phi, hipStream_t s);
 // Y = b - M X (residual) or Y = M X; adjoint applies M^H.  k columns per shift.
 // Bm's blocks are bstride elements apart (0: one block shared by every shift).
+// skip: optional device word; when non-zero at run time the kernel does nothing.
 hipError_t launch_apply(const OpDesc& op, const double* omega /*dev 2*n_omega*/, int n_omega,
                         int k, int adjoint, const double* X, const double* Bm, int64_t bstride,
-                        double* Y, hipStream_t s);
+                        double* Y, hipStream_t s, const uint32_t* skip = nullptr);
 hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed,
                          double* Theta, hipStream_t s);
 
@@ -129,7 +111,7 @@ int solve_np(int k);
 hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
                         double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
-                        int grid, hipStream_t s);
+                        int grid, hipStream_t s, const uint32_t* skip = nullptr);
 
 // Small dense / tall-skinny kernels (rr_small.hip)
 struct SmallWs {   // workspace for tall-skinny reductions
@@ -156,7 +138,8 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
 // X += D and per-column convergence test ||D_j|| <= tol ||X_j|| (latches status)
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D,
                                 double tol, SmallWs& ws, uint32_t* status,
-                                uint32_t* fail_count, hipStream_t s);
+                                uint32_t* fail_count, hipStream_t s,
+                                const uint32_t* skip = nullptr);
 // gradient kernel (rr_grad.hip)
 hipError_t launch_grad(int nx, int ny, double hx, double hy, int n_omega,
                        const double* omega, const double* sigma1, const double* u1,
@@ -175,7 +158,8 @@ struct rr_factors {
   int grid;        // persistent workgroups of the factorisation
   int solve_grid;  // persistent workgroups of a solve
   int refine_iters;
-  double refine_tol;
+  double refine_tol;         // projection / recovery solves
+  double refine_tol_sketch;  // sketch and subspace-iteration solves
   // private copies of the problem
   double* coef = nullptr;
   double* phi = nullptr;

@@ -63,7 +63,8 @@ hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, dou
 __global__ void k_apply(int nx, int ny, const double* __restrict__ coef,
                         const double* __restrict__ omega, int k, int adjoint,
                         const double2* __restrict__ X, const double2* __restrict__ Bm,
-                        int64_t bstride, double2* __restrict__ Y) {
+                        int64_t bstride, double2* __restrict__ Y, const uint32_t* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   int nn = nx * ny;
   if (p >= nn) return;
@@ -125,11 +126,11 @@ __global__ void k_apply(int nx, int ny, const double* __restrict__ coef,
 
 hipError_t launch_apply(const OpDesc& op, const double* omega, int n_omega, int k, int adjoint,
                         const double* X, const double* Bm, int64_t bstride, double* Y,
-                        hipStream_t s) {
+                        hipStream_t s, const uint32_t* skip) {
   int nn = op.nx * op.ny;
   dim3 grid((nn + 255) / 256, k, n_omega);
   hipLaunchKernelGGL(k_apply, grid, dim3(256), 0, s, op.nx, op.ny, op.coef, omega, k, adjoint,
-                     (const double2*)X, (const double2*)Bm, bstride, (double2*)Y);
+                     (const double2*)X, (const double2*)Bm, bstride, (double2*)Y, skip);
   return hipGetLastError();
 }
 

@@ -378,7 +378,8 @@ hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const do
 __global__ __launch_bounds__(256) void k_colnorm_partial(int64_t n, int k, double2* X,
                                                          const double2* __restrict__ D,
                                                          int nchunk, double* partial,
-                                                         double* partial2) {
+                                                         double* partial2, const uint32_t* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   __shared__ double red[2][256];
   const int w = blockIdx.y, chunk = blockIdx.x;
   int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
@@ -443,7 +444,8 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
   if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
   double* part = ws.partial;
   hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
-                     (double2*)W, (const double2*)nullptr, nc, part, (double*)nullptr);
+                     (double2*)W, (const double2*)nullptr, nc, part, (double*)nullptr,
+                     (const uint32_t*)nullptr);
   hipLaunchKernelGGL(k_colnorm_final, dim3(n_omega), dim3(64), 0, s, k, nc, part, sigma, status);
   if (U)
     hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, k, n_omega), dim3(256), 0, s,
@@ -454,7 +456,8 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
 // After X += D: a column has converged when ||D_j|| <= tol ||X_j||.  Counts
 // unconverged columns into *fail_count (reset by the caller per solve).
 __global__ void k_refine_check(int k, int nchunk, const double* px, const double* pd, double tol,
-                               uint32_t* fail_count, uint32_t* status) {
+                               uint32_t* fail_count, uint32_t* status, const uint32_t* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const int w = blockIdx.x;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
     double sx = 0, sd = 0;
@@ -469,15 +472,15 @@ __global__ void k_refine_check(int k, int nchunk, const double* px, const double
 
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D, double tol,
                                 SmallWs& ws, uint32_t* status, uint32_t* fail_count,
-                                hipStream_t s) {
+                                hipStream_t s, const uint32_t* skip) {
   int nc = nchunks(n);
   if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
   double* px = ws.partial;
   double* pd = ws.partial + (size_t)n_omega * nc * 64;
   hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
-                     (double2*)X, (const double2*)D, nc, px, pd);
+                     (double2*)X, (const double2*)D, nc, px, pd, skip);
   hipLaunchKernelGGL(k_refine_check, dim3(n_omega), dim3(64), 0, s, k, nc, px, pd, tol,
-                     fail_count, status);
+                     fail_count, status, skip);
   return hipGetLastError();
 }
 

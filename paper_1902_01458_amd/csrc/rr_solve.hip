@@ -16,8 +16,9 @@
 // s (published long ago) are consumed first and only the product with the
 // immediate predecessor waits on the critical path.  The sweep's intermediate
 // blocks live in a row-major workspace (T rows x NP columns per block) so the
-// operand loads of all waves are coalesced; they are written with agent-scope
-// stores so the release before each flag has little to write back.
+// operand loads of all waves are coalesced.  Block s of the workspace holds
+// y_s in the first sweep and x_s in the second, so it is written with
+// device-coherent stores (st_coherent).
 #include "rr_mfma.h"
 
 namespace rr {
@@ -90,12 +91,12 @@ struct Solve2Params {
   uint32_t* ticket;
   uint32_t* status;
   int64_t total;     // n_omega * 2 * NB
+  const uint32_t* skip;  // optional: non-zero at run time = nothing to do
 };
 
 // Thread 0 polls flags [t0, t1] of one shift until each reaches `want`, then
 // issues one acquire fence; the barrier hands the result to every wave.
 __device__ __forceinline__ void wg_wait_range(int* fl, int t0, int t1, int want, uint32_t* status) {
-  __shared__ int dummy;
   if (threadIdx.x == 0) {
     bool live = !(__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT);
     uint64_t t_start = wall_clock64();
@@ -111,7 +112,6 @@ __device__ __forceinline__ void wg_wait_range(int* fl, int t0, int t1, int want,
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    dummy = 0;
   }
   __syncthreads();
 }
@@ -131,6 +131,7 @@ __device__ __forceinline__ void wg_publish_one(int* flag, int value) {
 
 template <typename R, int T, int NP, bool ADJ>
 __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Params P) {
+  if (P.skip && __hip_atomic_load(P.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   constexpr int NCB = NP / 16;
   extern __shared__ __align__(16) char solve_smem[];
   cplx<R>* blk = reinterpret_cast<cplx<R>*>(solve_smem);  // pre-diagonal block, row-major
@@ -229,9 +230,7 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     cplx<R>* xs = xw + (int64_t)s * T * NP;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-      cplx<R>* d = xs + (16 * rb + Mf<R>::row(l, e)) * NP + j;
-      __hip_atomic_store(&d->re, are[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&d->im, aim[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_coherent(xs + (16 * rb + Mf<R>::row(l, e)) * NP + j, cplx<R>{are[e], aim[e]});
     }
     if (second) {
       double2* Xw = P.X + (int64_t)w * P.k * P.n;
@@ -277,11 +276,11 @@ int solve_np(int k) { return ((k + 15) / 16) * 16; }
 hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
                         double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
-                        int grid, hipStream_t s) {
+                        int grid, hipStream_t s, const uint32_t* skip) {
   int NP = solve_np(k);
   if (NP > 64 || (g.T == 64 && NP > 64) || (g.T * NP > 64 * 64)) return hipErrorInvalidValue;
   Solve2Params P{g, n, n_omega, k, adjoint, tiles, (const double2*)Bm, bstride, (double2*)X,
-                 xs, flags, ticket, status, (int64_t)n_omega * 2 * g.NB};
+                 xs, flags, ticket, status, (int64_t)n_omega * 2 * g.NB, skip};
   hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.NB, s);
   if (e == hipSuccess) e = launch_fill_u32(ticket, 0u, 1, s);
   if (e != hipSuccess) return e;
