@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-shifts", type=int, default=1)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size "
+                         "kernel for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -130,6 +133,12 @@ def main():
     import workloads as W
     w = W.CONFIGS[args.workload]
     torch.cuda.init()
+    if args.copy_calibration_mib:
+        src = torch.ones(args.copy_calibration_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = rr.BurgersProblem.from_workload(w)
     torch.cuda.synchronize()
     gold = json.load(open(GOLDEN)) if (os.path.exists(GOLDEN) and args.workload == "cfg1_batch16") \
