@@ -29,6 +29,21 @@
 // from the stencil in registers: the band is never read before it is final.
 // Every tile store is device-coherent (st_coherent): a tile is written twice
 // per launch, from different XCDs in general, and read from others.
+//
+// Chain tiles.  In each sweep of a solve, block s depends on the blocks t
+// within B of it through x_s = D^-1 (b_s - sum_t T_st x_t), D^-1 a triangle of
+// the diagonal inverse.  For the two nearest neighbours (distance d = 1, 2)
+// the factorisation stores the products G_s,d = D^-1 T_s,s-+d, so that a solve
+// step applies D^-1 to the far terms three or more blocks back, before either
+// neighbour is ready, and the two products left after that are register MFMAs
+// with no LDS round trip:  x_s = D^-1 (b_s - sum_far) - G_s,2 x_s-+2 - G_s,1 x_s-+1.
+//   CH_FWD_L,d = L_ss^-1 L_s,s-d   (column-major)   forward, L sweep
+//   CH_FWD_U,d = U_ss^-1 U_s,s+d   (column-major)   forward, U sweep
+//   CH_ADJ_U,d = U_s-d,s U_ss^-1   (row-major)      adjoint, U^H sweep (used as ^H)
+//   CH_ADJ_L,d = L_s+d,s L_ss^-1   (row-major)      adjoint, L^H sweep (used as ^H)
+// F(s, s) forms CH_FWD_L and CH_ADJ_U after publishing D_s; F(s+d, s) and
+// F(s, s+d) form CH_ADJ_L,d and CH_FWD_U,d after publishing their tile.
+// Nothing in the launch waits on chain tiles.
 #include "rr_mfma.h"
 
 namespace rr {
@@ -163,16 +178,24 @@ __device__ __forceinline__ int tix(int i, int j, int T, bool rowmajor) {
   return rowmajor ? i * T + j : j * T + i;
 }
 
-// acc (+/-)= A * B for T x T tiles.  A: column-major (A[i][k] at k*lda + i);
-// B: row-major (B[k][j] at k*ldb + j) or column-major (at j*ldb + k); either
-// may live in LDS or global memory.  Optional triangular masks apply to the
-// stored tile's own indices.  Fragments of KQ k-steps are loaded before use.
+// acc (+/-)= A * B for T x T tiles.  A: column-major (A[i][k] at k*lda + i)
+// or row-major (at i*lda + k); B: row-major (B[k][j] at k*ldb + j) or
+// column-major (at j*ldb + k); either may live in LDS or global memory.
+// Optional triangular masks apply to each stored tile's own indices.
+// Fragments of KQ k-steps are loaded before use.
 enum { MK_NONE = 0, MK_UNIT_LOWER = 1, MK_UPPER = 2 };
 
+template <typename R>
+__device__ __forceinline__ cplx<R> apply_mask(cplx<R> v, int mask, int row, int col) {
+  if (mask == MK_UNIT_LOWER && row <= col) return cplx<R>{row == col ? (R)1 : (R)0, (R)0};
+  if (mask == MK_UPPER && row > col) return cplx<R>{(R)0, (R)0};
+  return v;
+}
+
 template <typename R, int T, int KQ, bool SUB>
-__device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int lda, int amask,
-                                          const cplx<R>* Bm, int ldb, bool b_colmajor, int bmask,
-                                          int rb, int cp) {
+__device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int lda, bool a_rowmajor,
+                                          int amask, const cplx<R>* Bm, int ldb, bool b_colmajor,
+                                          int bmask, int rb, int cp) {
   const int l = threadIdx.x & 63;
   const int i = 16 * rb + (l & 15);
   const int j0 = 32 * cp + (l & 15), j1 = j0 + 16;
@@ -182,7 +205,7 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
 #pragma unroll
     for (int q = 0; q < KQ; q++) {
       const int k = 4 * (kq + q) + (l >> 4);
-      a[q] = A[k * lda + i];
+      a[q] = a_rowmajor ? A[i * lda + k] : A[k * lda + i];
       b0[q] = b_colmajor ? Bm[j0 * ldb + k] : Bm[k * ldb + j0];
       b1[q] = b_colmajor ? Bm[j1 * ldb + k] : Bm[k * ldb + j1];
     }
@@ -190,9 +213,9 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
 #pragma unroll
       for (int q = 0; q < KQ; q++) {
         const int k = 4 * (kq + q) + (l >> 4);
-        if (amask == MK_UNIT_LOWER && i <= k) a[q] = cplx<R>{i == k ? (R)1 : (R)0, (R)0};
-        if (bmask == MK_UPPER && k > j0) b0[q] = cplx<R>{(R)0, (R)0};
-        if (bmask == MK_UPPER && k > j1) b1[q] = cplx<R>{(R)0, (R)0};
+        a[q] = apply_mask(a[q], amask, i, k);
+        b0[q] = apply_mask(b0[q], bmask, k, j0);
+        b1[q] = apply_mask(b1[q], bmask, k, j1);
       }
     }
 #pragma unroll
@@ -236,8 +259,13 @@ __device__ __forceinline__ bool has_early(int r, int t, int B) {
 
 template <typename R, int T>
 __device__ __forceinline__ cplx<R>* tile_ptr(const FactorParams& P, int w, int r, int t) {
-  const int W = 2 * P.g.B + 1;
-  int64_t idx = ((int64_t)w * P.g.NB + r) * W + (t - r + P.g.B);
+  int64_t idx = ((int64_t)w * P.g.NB + r) * P.g.row_tiles() + (t - r + P.g.B);
+  return reinterpret_cast<cplx<R>*>(P.tiles) + idx * (T * T);
+}
+// Chain tile `c` of block row s (CH_* below).
+template <typename R, int T>
+__device__ __forceinline__ cplx<R>* chain_ptr(const FactorParams& P, int w, int s, int c) {
+  int64_t idx = ((int64_t)w * P.g.NB + s) * P.g.row_tiles() + 2 * P.g.B + 1 + c;
   return reinterpret_cast<cplx<R>*>(P.tiles) + idx * (T * T);
 }
 __device__ __forceinline__ int* flag_ptr(const FactorParams& P, int w, int r, int t) {
@@ -380,7 +408,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     int* dflag = (!early && r != t) ? flag_ptr(P, w, m, m) : nullptr;
     if (s_lo <= s_hi || dflag) wait_inputs(P, w, r, t, s_lo, s_hi, dflag, 2);
     for (int s = s_lo; s <= s_hi; s++)
-      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, r, s), T, MK_NONE,
+      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, r, s), T, false, MK_NONE,
                                 tile_ptr<R, T>(P, w, s, t), T, false, MK_NONE, rb, cp);
     if (early) {
       acc_to_tile<R, T>(acc, X, rowmajor, rb, cp);
@@ -400,17 +428,49 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       acc_to_lds<R, T>(acc, lds, false, rb, cp);
       __syncthreads();
       acc.zero();
-      tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, MK_NONE, D, T, true, MK_UPPER, rb, cp);
+      tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_NONE, D, T, true, MK_UPPER, rb, cp);
       acc_to_tile<R, T>(acc, X, false, rb, cp);
     } else {
       // U_mt = L_mm^-1 A_mt: L^-1 = unit-lower part of D, A from LDS (row-major)
       acc_to_lds<R, T>(acc, lds, true, rb, cp);
       __syncthreads();
       acc.zero();
-      tile_gemm<R, T, KQ, false>(acc, D, T, MK_UNIT_LOWER, lds, G::LDT, false, MK_NONE, rb, cp);
+      tile_gemm<R, T, KQ, false>(acc, D, T, false, MK_UNIT_LOWER, lds, G::LDT, false, MK_NONE, rb,
+                                 cp);
       acc_to_tile<R, T>(acc, X, true, rb, cp);
     }
     publish(flag_ptr(P, w, r, t), 2);
+    // 4. chain tiles (off the dependency chain: published data first)
+    const int d = mx - m;
+    if (r == t) {
+      for (int dd = 1; dd <= 2 && dd <= B && m - dd >= 0; dd++) {
+        // L_mm^-1 L_m,m-dd and U_m-dd,m U_mm^-1, with D still in LDS
+        acc.zero();
+        tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_UNIT_LOWER,
+                                   tile_ptr<R, T>(P, w, m, m - dd), T, true, MK_NONE, rb, cp);
+        acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_L, dd)), false, rb,
+                          cp);
+        acc.zero();
+        tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, m - dd, m), T, true, MK_NONE, lds,
+                                   G::LDT, true, MK_UPPER, rb, cp);
+        acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_U, dd)), true, rb, cp);
+      }
+    } else if (d <= 2 && r > t) {
+      // L_m+d,m L_mm^-1: the new L tile (still in acc) goes to LDS
+      acc_to_lds<R, T>(acc, lds, false, rb, cp);
+      __syncthreads();
+      acc.zero();
+      tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_NONE, D, T, true, MK_UNIT_LOWER, rb,
+                                 cp);
+      acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_L, d)), true, rb, cp);
+    } else if (d <= 2) {
+      // U_mm^-1 U_m,m+d: the new U tile (still in acc) goes to LDS
+      acc_to_lds<R, T>(acc, lds, true, rb, cp);
+      __syncthreads();
+      acc.zero();
+      tile_gemm<R, T, KQ, false>(acc, D, T, false, MK_UPPER, lds, G::LDT, false, MK_NONE, rb, cp);
+      acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_U, d)), false, rb, cp);
+    }
   }
 }
 

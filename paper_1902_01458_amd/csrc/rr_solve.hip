@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
   typedef typename Mf<R>::v4 v4;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rb = wave / NCB, cb = wave % NCB;
-  const int B = P.g.B, NB = P.g.NB, W = 2 * B + 1;
+  const int B = P.g.B, NB = P.g.NB, RT = P.g.row_tiles();
   for (;;) {
     const int64_t ticket = wg_ticket(P.ticket, &s_ticket);
     if (ticket >= P.total) break;
@@ -149,8 +149,9 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     const int s = second ? (int)(2 * NB - 1 - task) : (int)task;
     int* fl = P.flags + (int64_t)w * NB;
     const cplx<R>* tw =
-        reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)w * NB * W * (T * T);
-    auto tile = [&](int r, int t) { return tw + ((int64_t)r * W + (t - r + B)) * (T * T); };
+        reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)w * NB * RT * (T * T);
+    auto tile = [&](int r, int t) { return tw + ((int64_t)r * RT + (t - r + B)) * (T * T); };
+    auto chain = [&](int r, int c) { return tw + ((int64_t)r * RT + 2 * B + 1 + c) * (T * T); };
     cplx<R>* xw = reinterpret_cast<cplx<R>*>(P.xs) + (int64_t)w * NB * T * NP;
     const int j = 16 * cb + (l & 15);  // this lane's column in the block
     v4 are, aim;
@@ -175,58 +176,74 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
         aim[e] = (R)v.y;
       }
     }
-    // off-diagonal products
-    //   forward first: L_st (t < s); forward second: U_st (t > s)
-    //   adjoint first: U_ts^H (t < s); adjoint second: L_ts^H (t > s)
-    // The operands of the two products on the critical path (the neighbour
-    // block and the diagonal inverse) are fetched before any wait: they are
-    // factor data, final before the launch.
+    // x_s = D_s^-1 (b_s - sum_{|t-s|>=3} T_st x_t) - G_s,2 x_s-+2 - G_s,1 x_s-+1
+    // (G: the chain tiles of rr_band.hip).  Far blocks were published long
+    // ago; D_s^-1 goes through LDS (every wave needs the whole column block);
+    // then the two neighbours, each one register MFMA product.
+    //   forward first: L_st (t < s), D = L^-1, G = CH_FWD_L
+    //   forward second: U_st (t > s), D = U^-1, G = CH_FWD_U
+    //   adjoint first: U_ts^H (t < s), D = (U^-1)^H, G = CH_ADJ_U^H
+    //   adjoint second: L_ts^H (t > s), D = (L^-1)^H, G = CH_ADJ_L^H
     const int want = second ? 2 : 1;
     const int dir = second ? 1 : -1;
-    const int near = s + dir;
-    const bool has_near = near >= 0 && near < NB;
     const int mask = (ADJ ? second : !second) ? OPM_UNIT_LOWER : OPM_UPPER;
     const bool ut = ADJ != second;  // off-diagonal tiles of this sweep are U tiles (row-major)
-    // the diagonal inverse is prefetched too where registers allow (FP32, or
-    // the 32-wide tile); otherwise it is read after the critical product
-    constexpr bool kPreDiag = sizeof(R) == 4 || T == 32;
-    Frag<R, T> a_near, a_diag, fb;
-    if (has_near) load_a<R, T, ADJ>(a_near, ADJ ? tile(near, s) : tile(s, near), OPM_NONE, rb, ut);
-    if (kPreDiag) load_a<R, T, ADJ>(a_diag, tile(s, s), mask, rb);
-    // far blocks (|t - s| >= 3), then the block two away, then the neighbour
+    const int kind = ADJ ? (second ? CH_ADJ_L : CH_ADJ_U) : (second ? CH_FWD_U : CH_FWD_L);
+    Frag<R, T> fb;
     int f0, f1;
     if (second) { f0 = s + 3; f1 = min(NB - 1, s + B); } else { f0 = max(0, s - B); f1 = s - 3; }
     if (f0 <= f1) {
-      wg_wait_range(fl, f0, f1, want, P.status);
-      for (int t = f0; t <= f1; t++) {
-        Frag<R, T> fa;
-        load_a<R, T, ADJ>(fa, ADJ ? tile(t, s) : tile(s, t), OPM_NONE, rb, ut);
-        load_b<R, T, NP>(fb, xw + (int64_t)t * T * NP, cb);
-        mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
+      // the older far blocks were published at least a step before the one
+      // three away: take them first, then wait for that one alone
+      const int fn = second ? f0 : f1;
+      const int g0 = second ? f0 + 1 : f0, g1 = second ? f1 : f1 - 1;
+      if (g0 <= g1) {
+        wg_wait_range(fl, g0, g1, want, P.status);
+        for (int t = g0; t <= g1; t++) {
+          Frag<R, T> fa;
+          load_a<R, T, ADJ>(fa, ADJ ? tile(t, s) : tile(s, t), OPM_NONE, rb, ut);
+          load_b<R, T, NP>(fb, xw + (int64_t)t * T * NP, cb);
+          mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
+        }
       }
-    }
-    const int mid = s + 2 * dir;
-    if (B >= 2 && mid >= 0 && mid < NB) {
-      wg_wait_range(fl, mid, mid, want, P.status);
       Frag<R, T> fa;
-      load_a<R, T, ADJ>(fa, ADJ ? tile(mid, s) : tile(s, mid), OPM_NONE, rb, ut);
-      load_b<R, T, NP>(fb, xw + (int64_t)mid * T * NP, cb);
+      load_a<R, T, ADJ>(fa, ADJ ? tile(fn, s) : tile(s, fn), OPM_NONE, rb, ut);
+      wg_wait_range(fl, fn, fn, want, P.status);
+      load_b<R, T, NP>(fb, xw + (int64_t)fn * T * NP, cb);
       mma_frag<R, T, ADJ, true>(are, aim, fa, fb);
     }
-    if (has_near) {
-      wg_wait_range(fl, near, near, want, P.status);
-      load_b<R, T, NP>(fb, xw + (int64_t)near * T * NP, cb);
-      mma_frag<R, T, ADJ, true>(are, aim, a_near, fb);
-    }
-    // diagonal block: x_s = D_s^-1 acc  (forward: L^-1 then U^-1; adjoint:
-    // (U^-1)^H then (L^-1)^H, all read from the stored inverse tile)
 #pragma unroll
     for (int e = 0; e < 4; e++) blk[(16 * rb + Mf<R>::row(l, e)) * NP + j] = cplx<R>{are[e], aim[e]};
     __syncthreads();
     for (int e = 0; e < 4; e++) { are[e] = 0; aim[e] = 0; }
-    if (!kPreDiag) load_a<R, T, ADJ>(a_diag, tile(s, s), mask, rb);
-    load_b<R, T, NP>(fb, blk, cb);
-    mma_frag<R, T, ADJ, false>(are, aim, a_diag, fb);
+    {
+      Frag<R, T> a_diag;
+      load_a<R, T, ADJ>(a_diag, tile(s, s), mask, rb);
+      load_b<R, T, NP>(fb, blk, cb);
+      mma_frag<R, T, ADJ, false>(are, aim, a_diag, fb);
+    }
+    // the neighbours at distance 2, then 1.  Chain tiles are factor data,
+    // final before the launch: their loads overlap the waits (a task is
+    // normally taken well before its neighbours are published).
+    const int nb1 = s + dir, nb2 = s + 2 * dir;
+    const bool has1 = nb1 >= 0 && nb1 < NB, has2 = B >= 2 && nb2 >= 0 && nb2 < NB;
+    // (in FP64 both chain fragments at once would not fit the register budget;
+    // the distance-1 one is then fetched after the distance-2 product)
+    constexpr bool kBoth = sizeof(R) == 4;
+    Frag<R, T> a1, a2;
+    if (has2) load_a<R, T, ADJ>(a2, chain(s, chain_index(kind, 2)), OPM_NONE, rb, ADJ);
+    if (kBoth && has1) load_a<R, T, ADJ>(a1, chain(s, chain_index(kind, 1)), OPM_NONE, rb, ADJ);
+    if (has2) {
+      wg_wait_range(fl, nb2, nb2, want, P.status);
+      load_b<R, T, NP>(fb, xw + (int64_t)nb2 * T * NP, cb);
+      mma_frag<R, T, ADJ, true>(are, aim, a2, fb);
+    }
+    if (!kBoth && has1) load_a<R, T, ADJ>(a1, chain(s, chain_index(kind, 1)), OPM_NONE, rb, ADJ);
+    if (has1) {
+      wg_wait_range(fl, nb1, nb1, want, P.status);
+      load_b<R, T, NP>(fb, xw + (int64_t)nb1 * T * NP, cb);
+      mma_frag<R, T, ADJ, true>(are, aim, a1, fb);
+    }
     cplx<R>* xs = xw + (int64_t)s * T * NP;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
