@@ -91,70 +91,289 @@ __device__ __forceinline__ double2 m_entry(const OpDesc& op, double om_r, double
   return make_double2(re, im);
 }
 
-// In-LDS no-pivot LU of the T x T tile S (column-major, leading dimension
-// LD), then in-place inversion of both triangles:
-//   S <- [U^-1 on and above the diagonal | L^-1 strictly below].
-template <typename R, int T, int NT>
-__device__ void lu_inv_tile(cplx<R>* S, int LD, cplx<R>* tmpL, cplx<R>* tmpU, uint32_t* status) {
-  auto at = [&](int i, int j) -> cplx<R>& { return S[j * LD + i]; };
-  for (int j = 0; j < T; j++) {
-    cplx<R> piv = at(j, j);
-    R mag = piv.re * piv.re + piv.im * piv.im;
-    bool bad = !(mag > (R)0) || !isfinite(mag);
-    if (bad) {
-      if (threadIdx.x == 0) latch(status, ST_SINGULAR);
-      piv = cplx<R>{(R)1, (R)0};
+// Triangular masks on a stored tile's own indices (row, col).
+enum { MK_NONE = 0, MK_UNIT_LOWER = 1, MK_UPPER = 2 };
+
+template <typename R>
+__device__ __forceinline__ cplx<R> apply_mask(cplx<R> v, int mask, int row, int col) {
+  if (mask == MK_UNIT_LOWER && row <= col) return cplx<R>{row == col ? (R)1 : (R)0, (R)0};
+  if (mask == MK_UPPER && row > col) return cplx<R>{(R)0, (R)0};
+  return v;
+}
+
+// Value of lane `src` (wave-uniform) in every lane.
+__device__ __forceinline__ float bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> bcast(cplx<R> v, int src) {
+  return cplx<R>{bcast(v.re, src), bcast(v.im, src)};
+}
+
+template <typename R>
+__device__ __forceinline__ void csub_mul(cplx<R>& x, cplx<R> a, cplx<R> b) {  // x -= a b
+  x.re -= a.re * b.re - a.im * b.im;
+  x.im -= a.re * b.im + a.im * b.re;
+}
+
+// (re, im) (+/-)= A * B for one 16 x 16 output block with K = 4q terms, both
+// operands column-major in LDS: A[i][k] at (ac + k) * lda + ar + i, B[k][j] at
+// (bc + j) * ldb + br + k.  Masks apply to each operand's own coordinates.
+template <typename R, bool SUB>
+__device__ __forceinline__ void lds_blk_gemm(typename Mf<R>::v4& re, typename Mf<R>::v4& im,
+                                             const cplx<R>* A, int lda, int ar, int ac, int amask,
+                                             const cplx<R>* Bm, int ldb, int br, int bc, int bmask,
+                                             int K) {
+  const int l = threadIdx.x & 63;
+#pragma unroll 1
+  for (int q = 0; q < K / 4; q++) {
+    const int k = 4 * q + (l >> 4);
+    cplx<R> a = apply_mask(A[(ac + k) * lda + ar + (l & 15)], amask, ar + (l & 15), ac + k);
+    cplx<R> b = apply_mask(Bm[(bc + (l & 15)) * ldb + br + k], bmask, br + k, bc + (l & 15));
+    cmfma<R, false, SUB>(re, im, a, b);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void blk_load(typename Mf<R>::v4& re, typename Mf<R>::v4& im,
+                                         const cplx<R>* S, int ld, int r0, int c0) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < 4; e++) {
+    cplx<R> v = S[(c0 + (l & 15)) * ld + r0 + Mf<R>::row(l, e)];
+    re[e] = v.re;
+    im[e] = v.im;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void blk_store(const typename Mf<R>::v4& re,
+                                          const typename Mf<R>::v4& im, cplx<R>* S, int ld,
+                                          int r0, int c0) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int e = 0; e < 4; e++)
+    S[(c0 + (l & 15)) * ld + r0 + Mf<R>::row(l, e)] = cplx<R>{re[e], im[e]};
+}
+
+// No-pivot LU of the T x T tile S (LDS, column-major, leading dimension LD)
+// and in-place inversion of both triangles,
+//   S <- [U^-1 on and above the diagonal | L^-1 strictly below],
+// blocked so that the sequential part is short and wave-local:
+//  LU, per 16-column panel: one wave factors the panel (lane = row, the
+//    pivot row broadcast lane to lane, no barriers), then U12 = L11^-1 A12 by
+//    forward substitution (thread = column), then A22 -= L21 U12 on MFMA;
+//  inverses: the 16 x 16 diagonal blocks by substitution (one wave each),
+//    then doubling: [[A, 0], [C, D]]^-1 has lower-left -D^-1 C A^-1, and
+//    [[A, B], [0, D]]^-1 upper-right -A^-1 B D^-1, two MFMA products per level
+//    (tmp: T*T/2 complex of LDS for the intermediate products).
+// A zero or non-finite pivot latches ST_SINGULAR and is replaced by 1.
+template <typename R, int T, int NW>
+__device__ void lu_inv_tile(cplx<R>* S, int LD, cplx<R>* tmp, uint32_t* status) {
+  typedef typename Mf<R>::v4 v4;
+  constexpr int P = 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const cplx<R> one{(R)1, (R)0}, zero{(R)0, (R)0};
+  auto at = [&](int i, int c) -> cplx<R>& { return S[c * LD + i]; };
+  // panel rows and U12 columns in registers where the budget allows (the FP64
+  // 64-wide kernel keeps the panel in LDS: its sixteen-value rows would spill)
+  constexpr bool kRegPanel = sizeof(R) == 4 || T == 32;
+  constexpr bool kRegTrsm = true;
+#pragma unroll 1
+  for (int c0 = 0; c0 < T; c0 += P) {
+    if (kRegPanel) {
+      // panel in registers: lane = row c0 + lane, the pivot row broadcast
+      // lane to lane (no LDS round trip per step)
+      if (wave == 0) {
+        const int r = c0 + lane;
+        const bool act = r < T;
+        cplx<R> a[P];
+#pragma unroll
+        for (int c = 0; c < P; c++) a[c] = act ? at(r, c0 + c) : zero;
+#pragma unroll
+        for (int j = 0; j < P; j++) {
+          cplx<R> p = bcast(a[j], j);
+          const R mag = p.re * p.re + p.im * p.im;
+          if (!(mag > (R)0) || !isfinite(mag)) {
+            if (lane == 0) latch(status, ST_SINGULAR);
+            if (lane == j) a[j] = one;
+            p = one;
+          }
+          const cplx<R> l = cmul(a[j], cinv(p));
+          const bool below = act && lane > j;
+          if (below) a[j] = l;
+#pragma unroll
+          for (int c = j + 1; c < P; c++) {
+            const cplx<R> u = bcast(a[c], j);
+            if (below) csub_mul(a[c], l, u);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int c = 0; c < P; c++)
+          if (act) at(r, c0 + c) = a[c];
+      }
+    } else {
+      // panel: one wave, lane = row c0 + lane.  Step j writes only rows below
+      // the pivot, each lane its own row, and reads the pivot row, so the
+      // steps need no barrier (one wave: LDS keeps issue order).
+      if (wave == 0) {
+        const int i = c0 + lane;
+#pragma unroll 1
+        for (int j = c0; j < c0 + P; j++) {
+          cplx<R> p = at(j, j);
+          const R mag = p.re * p.re + p.im * p.im;
+          if (!(mag > (R)0) || !isfinite(mag)) {
+            if (lane == 0) {
+              latch(status, ST_SINGULAR);
+              at(j, j) = one;
+            }
+            p = one;
+          }
+          if (i > j && i < T) {
+            const cplx<R> l = cmul(at(i, j), cinv(p));
+            at(i, j) = l;
+#pragma unroll 4
+            for (int c = j + 1; c < c0 + P; c++) csub_mul(at(i, c), l, at(j, c));
+          }
+        }
+      }
     }
-    cplx<R> ip = cinv(piv);
     __syncthreads();
-    if (bad && threadIdx.x == 0) at(j, j) = piv;
-    for (int i = j + 1 + threadIdx.x; i < T; i += NT) at(i, j) = cmul(at(i, j), ip);
+    if (c0 + P >= T) break;
+    if (kRegTrsm) {
+      // U12 = L11^-1 A12: thread t owns column c0 + P + t, held in registers
+      if (threadIdx.x < T - c0 - P) {
+        const int c = c0 + P + threadIdx.x;
+        cplx<R> x[P];
+#pragma unroll
+        for (int i = 0; i < P; i++) x[i] = at(c0 + i, c);
+#pragma unroll
+        for (int j = 0; j < P - 1; j++) {
+#pragma unroll
+          for (int i = j + 1; i < P; i++) csub_mul(x[i], at(c0 + i, c0 + j), x[j]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int i = 0; i < P; i++) at(c0 + i, c) = x[i];
+      }
+    } else {
+      // U12 = L11^-1 A12: thread t owns column c0 + P + t (writes only that column)
+      if (threadIdx.x < T - c0 - P) {
+        const int c = c0 + P + threadIdx.x;
+#pragma unroll 1
+        for (int j = c0; j < c0 + P - 1; j++) {
+          const cplx<R> xj = at(j, c);
+#pragma unroll 4
+          for (int i = j + 1; i < c0 + P; i++) csub_mul(at(i, c), at(i, j), xj);
+        }
+      }
+    }
     __syncthreads();
-    int w = T - 1 - j;
-    for (int idx = threadIdx.x; idx < w * w; idx += NT) {
-      int i = j + 1 + idx % w, c = j + 1 + idx / w;
-      cplx<R> l = at(i, j), u = at(j, c), x = at(i, c);
-      x.re -= l.re * u.re - l.im * u.im;
-      x.im -= l.re * u.im + l.im * u.re;
-      at(i, c) = x;
+    // A22 -= L21 U12 in 16 x 16 blocks
+    const int nb = (T - c0 - P) / 16;
+    for (int b = wave; b < nb * nb; b += NW) {
+      const int bi = c0 + P + 16 * (b % nb), bj = c0 + P + 16 * (b / nb);
+      v4 re, im;
+      blk_load<R>(re, im, S, LD, bi, bj);
+      lds_blk_gemm<R, true>(re, im, S, LD, bi, c0, MK_NONE, S, LD, c0, bj, MK_NONE, P);
+      blk_store<R>(re, im, S, LD, bi, bj);
     }
     __syncthreads();
   }
-  // L^-1 (ascending j) and U^-1 (descending jj = T-1-j) touch disjoint
-  // triangles, so both advance in the same loop.
-  for (int j = 0; j < T; j++) {
-    int jj = T - 1 - j;
-    cplx<R> iu = cinv(at(jj, jj));
-    for (int i = threadIdx.x; i < T; i += NT) {
-      if (i > j) tmpL[i] = at(i, j);      // multipliers L[i][j]
-      if (i < jj) tmpU[i] = at(i, jj);    // multipliers U[i][jj]
+  // inverses of the 16 x 16 diagonal blocks, in place, one wave per block
+  // (tasks 0 .. T/16-1: L blocks, the rest U blocks).  Each step reads all
+  // its operands before any lane stores (one wave: LDS keeps issue order).
+  constexpr int NDB = T / 16;
+  for (int tsk = wave; tsk < 2 * NDB; tsk += NW) {
+    const bool isL = tsk < NDB;
+    const int b0 = 16 * (isL ? tsk : tsk - NDB);
+    auto bt = [&](int i, int c) -> cplx<R>& { return S[(b0 + c) * LD + b0 + i]; };
+#pragma unroll 1
+    for (int st = 0; st < 16; st++) {
+      cplx<R> nv[4];
+      bool wr[4];
+      if (isL) {
+        // step j = st: X[i][c] -= L[i][j] X[j][c] for i > j, c <= j (X[j][j] = 1)
+        const int jx = st;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int idx = lane + 64 * e, i = idx % 16, c = idx / 16;
+          wr[e] = i > jx && c <= jx;
+          const cplx<R> m = bt(i, jx);
+          const cplx<R> xj = (c == jx) ? one : bt(jx, c);
+          nv[e] = (c == jx) ? zero : bt(i, c);
+          csub_mul(nv[e], m, xj);
+        }
+      } else {
+        // step jj = 15 - st: row jj <- acc / U[jj][jj]; rows i < jj:
+        // acc[i][c] -= U[i][jj] X[jj][c] for c >= jj
+        const int jj = 15 - st;
+        const cplx<R> iu = cinv(bt(jj, jj));
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int idx = lane + 64 * e, i = idx % 16, c = idx / 16;
+          const cplx<R> xj = (c == jj) ? iu : cmul(bt(jj, c), iu);
+          wr[e] = i <= jj && c >= jj;
+          if (i == jj) {
+            nv[e] = xj;
+          } else {
+            nv[e] = (c == jj) ? zero : bt(i, c);
+            csub_mul(nv[e], bt(i, jj), xj);
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int idx = lane + 64 * e;
+        if (wr[e]) bt(idx % 16, idx / 16) = nv[e];
+      }
+    }
+  }
+  __syncthreads();
+  // doubling: blocks of 2h along the diagonal; kind 0 = L, 1 = U
+#pragma unroll 1
+  for (int h = 16; h < T; h *= 2) {
+    const int nblk = T / (2 * h), nsub = (h / 16) * (h / 16);
+    const int ntask = 2 * nblk * nsub;
+    for (int tsk = wave; tsk < ntask; tsk += NW) {
+      const int kind = tsk / (nblk * nsub), rem = tsk % (nblk * nsub);
+      const int blk = rem / nsub, sub = rem % nsub;
+      const int b0 = 2 * h * blk, si = 16 * (sub % (h / 16)), sj = 16 * (sub / (h / 16));
+      cplx<R>* t1 = tmp + (kind * nblk + blk) * h * h;
+      v4 re, im;
+#pragma unroll
+      for (int e = 0; e < 4; e++) { re[e] = 0; im[e] = 0; }
+      if (kind == 0)  // L21 L11^-1
+        lds_blk_gemm<R, false>(re, im, S, LD, b0 + h + si, b0, MK_NONE, S, LD, b0, b0 + sj,
+                               MK_UNIT_LOWER, h);
+      else            // U12 U22^-1
+        lds_blk_gemm<R, false>(re, im, S, LD, b0 + si, b0 + h, MK_NONE, S, LD, b0 + h,
+                               b0 + h + sj, MK_UPPER, h);
+      blk_store<R>(re, im, t1, h, si, sj);
     }
     __syncthreads();
-    // U: finalise row jj: X[jj][c] = acc[jj][c] / U[jj][jj]
-    for (int c = jj + 1 + threadIdx.x; c < T; c += NT) at(jj, c) = cmul(at(jj, c), iu);
-    if (threadIdx.x == 0) at(jj, jj) = iu;
-    __syncthreads();
-    // L: rows i > j, columns c <= j:  X[i][c] -= L[i][j] X[j][c]  (X[j][j] = 1)
-    int wl = T - 1 - j, hl = j + 1;
-    for (int idx = threadIdx.x; idx < wl * hl; idx += NT) {
-      int i = j + 1 + idx % wl, c = idx / wl;
-      cplx<R> m = tmpL[i];
-      cplx<R> xj = (c == j) ? cplx<R>{(R)1, (R)0} : at(j, c);
-      cplx<R> x = (c == j) ? cplx<R>{(R)0, (R)0} : at(i, c);
-      x.re -= m.re * xj.re - m.im * xj.im;
-      x.im -= m.re * xj.im + m.im * xj.re;
-      at(i, c) = x;
-    }
-    // U: rows i < jj, columns c >= jj:  acc[i][c] -= U[i][jj] X[jj][c]
-    int hu = jj, wu = T - jj;
-    for (int idx = threadIdx.x; idx < hu * wu; idx += NT) {
-      int i = idx % hu, c = jj + idx / hu;
-      cplx<R> m = tmpU[i];
-      cplx<R> xj = at(jj, c);
-      cplx<R> x = (c == jj) ? cplx<R>{(R)0, (R)0} : at(i, c);
-      x.re -= m.re * xj.re - m.im * xj.im;
-      x.im -= m.re * xj.im + m.im * xj.re;
-      at(i, c) = x;
+    for (int tsk = wave; tsk < ntask; tsk += NW) {
+      const int kind = tsk / (nblk * nsub), rem = tsk % (nblk * nsub);
+      const int blk = rem / nsub, sub = rem % nsub;
+      const int b0 = 2 * h * blk, si = 16 * (sub % (h / 16)), sj = 16 * (sub / (h / 16));
+      const cplx<R>* t1 = tmp + (kind * nblk + blk) * h * h;
+      v4 re, im;
+#pragma unroll
+      for (int e = 0; e < 4; e++) { re[e] = 0; im[e] = 0; }
+      if (kind == 0) {  // lower-left <- -L22^-1 (L21 L11^-1)
+        lds_blk_gemm<R, true>(re, im, S, LD, b0 + h + si, b0 + h, MK_UNIT_LOWER, t1, h, 0, sj,
+                              MK_NONE, h);
+        blk_store<R>(re, im, S, LD, b0 + h + si, b0 + sj);
+      } else {          // upper-right <- -U11^-1 (U12 U22^-1)
+        lds_blk_gemm<R, true>(re, im, S, LD, b0 + si, b0, MK_UPPER, t1, h, 0, sj, MK_NONE, h);
+        blk_store<R>(re, im, S, LD, b0 + si, b0 + h + sj);
+      }
     }
     __syncthreads();
   }
@@ -183,15 +402,6 @@ __device__ __forceinline__ int tix(int i, int j, int T, bool rowmajor) {
 // column-major (at j*ldb + k); either may live in LDS or global memory.
 // Optional triangular masks apply to each stored tile's own indices.
 // Fragments of KQ k-steps are loaded before use.
-enum { MK_NONE = 0, MK_UNIT_LOWER = 1, MK_UPPER = 2 };
-
-template <typename R>
-__device__ __forceinline__ cplx<R> apply_mask(cplx<R> v, int mask, int row, int col) {
-  if (mask == MK_UNIT_LOWER && row <= col) return cplx<R>{row == col ? (R)1 : (R)0, (R)0};
-  if (mask == MK_UPPER && row > col) return cplx<R>{(R)0, (R)0};
-  return v;
-}
-
 template <typename R, int T, int KQ, bool SUB>
 __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int lda, bool a_rowmajor,
                                           int amask, const cplx<R>* Bm, int ldb, bool b_colmajor,
@@ -356,7 +566,6 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
   extern __shared__ __align__(16) char smem_raw[];
   cplx<R>* lds = reinterpret_cast<cplx<R>*>(smem_raw);  // T x LDT
   __shared__ uint32_t s_ticket;
-  __shared__ cplx<R> tmpL[T], tmpU[T];
   const int B = P.g.B, NB = P.g.NB;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rb = wave / G::CPR, cp = wave % G::CPR;
@@ -375,6 +584,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     const int m = min(r, t), mx = max(r, t);
     const bool rowmajor = r < t;  // U tiles
     cplx<R>* X = tile_ptr<R, T>(P, w, r, t);
+
     // 1. the tile: the partial left by E(r, t), or generated from the stencil
     if (!early && has_early(r, t, B)) {
       wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), 1);
@@ -410,6 +620,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     for (int s = s_lo; s <= s_hi; s++)
       tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, r, s), T, false, MK_NONE,
                                 tile_ptr<R, T>(P, w, s, t), T, false, MK_NONE, rb, cp);
+
     if (early) {
       acc_to_tile<R, T>(acc, X, rowmajor, rb, cp);
       publish(flag_ptr(P, w, r, t), 1);
@@ -420,7 +631,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     if (r == t) {
       acc_to_lds<R, T>(acc, lds, false, rb, cp);
       __syncthreads();
-      lu_inv_tile<R, T, G::NT>(lds, G::LDT, tmpL, tmpU, P.status);
+      lu_inv_tile<R, T, G::NW>(lds, G::LDT, lds + T * G::LDT, P.status);
       for (int idx = threadIdx.x; idx < T * T; idx += G::NT)
         st_coherent(&X[idx], lds[(idx / T) * G::LDT + idx % T]);
     } else if (r > t) {
@@ -476,7 +687,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
 
 template <typename R, int T>
 static hipError_t launch_factor_t(const FactorParams& P, int grid, hipStream_t s) {
-  size_t lds = sizeof(cplx<R>) * (size_t)T * FGeom<T>::LDT;
+  size_t lds = sizeof(cplx<R>) * ((size_t)T * FGeom<T>::LDT + (size_t)T * T / 2);
   hipError_t e = hipFuncSetAttribute((const void*)k_factor<R, T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
