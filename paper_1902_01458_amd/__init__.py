@@ -10,6 +10,7 @@ HIP kernels of librr.so; this package only marshals arguments.
 """
 from .api import (BurgersProblem, Factors, factor, philox_raw, resolvent, sketch)  # noqa: F401
 from ._lib import RRError, lib  # noqa: F401
+from .autograd import SigmaOne, sigma_one  # noqa: F401
 
 __all__ = ["BurgersProblem", "Factors", "factor", "resolvent", "sketch", "philox_raw", "RRError",
-           "lib"]
+           "lib", "SigmaOne", "sigma_one"]

@@ -54,10 +54,17 @@ class BurgersProblem:
         return 2 * self.nx * self.ny
 
     @classmethod
-    def from_base_flow(cls, U: np.ndarray, nx: int, ny: int, domain, nu: float,
+    def from_base_flow(cls, U, nx: int, ny: int, domain, nu: float,
                        weighted: bool = True, device="cuda") -> "BurgersProblem":
-        """Coefficients and Phi computed on the GPU (rr_burgers_coeffs)."""
-        Ud = torch.as_tensor(np.ascontiguousarray(U, dtype=np.float64).reshape(-1), device=device)
+        """Coefficients and Phi computed on the GPU (rr_burgers_coeffs).  U is the
+        (nx+2, ny+2) base flow with its boundary ring, host array or GPU tensor."""
+        if isinstance(U, torch.Tensor) and U.is_cuda:
+            Ud = U.detach().to(torch.float64).contiguous().reshape(-1)
+        else:
+            Ud = torch.as_tensor(np.ascontiguousarray(U, dtype=np.float64).reshape(-1),
+                                 device=device)
+        if Ud.numel() != (nx + 2) * (ny + 2):
+            raise ValueError("U must have (nx+2)*(ny+2) values")
         coef = torch.empty(nx * ny * 12, dtype=torch.float64, device=device)
         phi = torch.empty(nx * ny, dtype=torch.float64, device=device) if weighted else None
         check(lib().rr_burgers_coeffs(nx, ny, _ptr(Ud), *map(float, domain), float(nu),

@@ -31,8 +31,7 @@ class SigmaOne(torch.autograd.Function):
         if not (U.is_cuda and U.dtype == torch.float64 and U.shape == (nx + 2, ny + 2)):
             raise ValueError("U must be a float64 CUDA tensor of shape (nx+2, ny+2)")
         om = omega.detach().cpu().numpy().astype(np.float64).reshape(-1)
-        prob = api.BurgersProblem.from_base_flow(U.detach().contiguous().cpu().numpy(), nx, ny,
-                                                 domain, float(nu), weighted=True)
+        prob = api.BurgersProblem.from_base_flow(U, nx, ny, domain, float(nu), weighted=True)
         f = api.factor(prob, om, precision, k_max=k, tile=tile)
         Q = f.sketch_solve(k, seed, q)
         Z = f.adjoint_solve(Q)
