@@ -35,7 +35,7 @@
  *     HIP device; "host" pointers are read before the call returns.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream). All work
  *     is ordered on it; entry points return before the GPU work completes,
- *     except rr_factors_create (host allocations) and rr_check (syncs).
+ *     except rr_check, rr_autotune and rr_factors_free (which synchronise).
  *   - The caller owns all input and output buffers; the library owns the
  *     rr_factors handle and everything it allocated for it.
  *   - Errors visible on the host (bad sizes, NULL pointers, allocation
@@ -45,9 +45,10 @@
  *     After an error the contents of the outputs are unspecified.
  *   - A handle is not thread-safe; distinct handles are independent.
  *   - No call allocates device memory except rr_factor (which sizes every
- *     workspace for k <= k_max) and rr_burgers_coeffs (none); so the
- *     sequence sketch_solve / adjoint_solve / gains / grad can be captured
- *     into a HIP graph.
+ *     workspace for k <= k_max) and rr_autotune (trial handles), and no
+ *     launch path makes a host-side runtime call, so the sequence refactor /
+ *     sketch_solve / adjoint_solve / gains / grad can be captured into a HIP
+ *     graph (rr_graph_capture does so for one pass of Algorithm 1).
  */
 #ifndef RR_H
 #define RR_H
@@ -212,6 +213,44 @@ size_t rr_bytes(const rr_factors* f);
 
 /* Free a handle (NULL-safe). Synchronises the device first. */
 void rr_factors_free(rr_factors* f);
+
+/* Device bytes rr_factor would allocate for these sizes (with phi and U),
+ * 0 for invalid sizes; tile 0 means the default.  A sweep too large for the
+ * device is split into chunks of shifts sized with it. */
+size_t rr_factor_bytes(int32_t nx, int32_t ny, int32_t n_omega, int32_t k_max, rr_precision prec,
+                       int32_t tile);
+
+/* Captured sweep: one pass of Algorithm 1 for every shift of the handle --
+ * optionally the refactorisation (refactor != 0, e.g. after the caller changed
+ * nothing but wants the factor re-timed, or to keep the whole pass in one
+ * graph), then rr_sketch_solve, rr_adjoint_solve and rr_gains with the
+ * arguments given here -- recorded once into a HIP graph and replayed with a
+ * single launch.  The buffers named at capture are the ones every replay
+ * reads and writes; the caller keeps them alive while the graph exists.
+ * Capture runs on a private stream, so no stream argument is taken; replays
+ * are ordered on the stream passed to rr_graph_launch, and their device-side
+ * status is latched in the handle as for the eager calls (rr_check).  The
+ * handle must outlive the graph.  Nothing is launched by rr_graph_capture. */
+typedef struct rr_graph rr_graph;
+rr_status rr_graph_capture(rr_factors* f, int32_t refactor, int32_t k, uint64_t seed, int32_t q,
+                           rr_response mode, double* Q, double* Z, double* sigma_B,
+                           double* sigma_AV, double* V, double* Uresp, rr_graph** out);
+rr_status rr_graph_launch(rr_graph* g, void* stream);
+void rr_graph_free(rr_graph* g);
+
+/* Autotuner for the band tile and the persistent grid: for each candidate
+ * (tile 64 or 32, one or two workgroups per CU) it builds a trial handle for
+ * this operator and the first max_shifts shifts (all when max_shifts <= 0),
+ * runs one warm-up pass and one timed pass of refactorisation, sketch solve
+ * and adjoint solve, and scores factor + 2.5 * (sketch + adjoint), the cost
+ * of one pass of Algorithm 1 with a subspace iteration.  The fastest
+ * candidate is written to *out (refinement fields zero: defaults) and its
+ * score in ms to *out_ms (may be NULL).  Candidates that do not fit in device
+ * memory are skipped.  Synchronises `stream`; allocates and frees its own
+ * trial handles and blocks; the caller's handles are untouched. */
+rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double* omega_im,
+                      int32_t n_omega, int32_t k, rr_precision prec, int32_t max_shifts,
+                      void* stream, rr_tuning* out, double* out_ms);
 
 /* Message for the last error returned on this thread (never NULL). */
 const char* rr_last_error(void);

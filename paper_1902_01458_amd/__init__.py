@@ -8,9 +8,11 @@ modes through eq. (9); plus mixed-precision refinement, batched frequency
 sweeps and the gradient of the leading gain.  All numerical work runs in the
 HIP kernels of librr.so; this package only marshals arguments.
 """
-from .api import (BurgersProblem, Factors, factor, philox_raw, resolvent, sketch)  # noqa: F401
+from .api import (BurgersProblem, Factors, Graph, autotune, capture, factor,  # noqa: F401
+                  factor_bytes, philox_raw, resolvent, sketch, sweep)
 from ._lib import RRError, lib  # noqa: F401
 from .autograd import SigmaOne, sigma_one  # noqa: F401
 
-__all__ = ["BurgersProblem", "Factors", "factor", "resolvent", "sketch", "philox_raw", "RRError",
-           "lib", "SigmaOne", "sigma_one"]
+__all__ = ["BurgersProblem", "Factors", "Graph", "factor", "resolvent", "sketch", "philox_raw",
+           "capture", "autotune", "sweep", "factor_bytes", "RRError", "lib", "SigmaOne",
+           "sigma_one"]

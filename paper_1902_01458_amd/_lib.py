@@ -17,7 +17,9 @@ RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
 # every symbol include/rr.h declares, plus the two test hooks of rr_operator.hip
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
            "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_grad", "rr_check", "rr_refine_count",
-           "rr_bytes", "rr_factors_free", "rr_last_error", "rr_philox_raw", "rr_sketch")
+           "rr_bytes", "rr_factors_free", "rr_factor_bytes", "rr_graph_capture",
+           "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
+           "rr_sketch")
 
 
 class RRError(RuntimeError):
@@ -73,6 +75,13 @@ def lib() -> ctypes.CDLL:
         "rr_philox_raw": [vp, i64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                           ctypes.c_uint32, vp],
         "rr_sketch": [pp, i32, u64, vp, vp],
+        "rr_factor_bytes": [i32, i32, i32, i32, ctypes.c_int, i32],
+        "rr_graph_capture": [vp, i32, i32, u64, i32, ctypes.c_int, vp, vp, vp, vp, vp, vp,
+                             ctypes.POINTER(vp)],
+        "rr_graph_launch": [vp, vp],
+        "rr_graph_free": [vp],
+        "rr_autotune": [pp, vp, vp, i32, i32, ctypes.c_int, i32, vp, ctypes.POINTER(Tuning),
+                        ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -81,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.rr_last_error.restype = ctypes.c_char_p
     L.rr_bytes.restype = ctypes.c_size_t
     L.rr_factors_free.restype = None
+    L.rr_factor_bytes.restype = ctypes.c_size_t
+    L.rr_graph_free.restype = None
     L.rr_refine_count.restype = ctypes.c_int32
     _lib = L
     return L

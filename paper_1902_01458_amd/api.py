@@ -218,6 +218,101 @@ class Factors:
         return dU, dnu, dom
 
 
+class Graph:
+    """One captured pass of Algorithm 1 over every shift of a handle
+    (rr_graph_capture); launch() replays it on a stream.  Holds references to
+    the handle and the buffers the graph writes."""
+
+    def __init__(self, f: "Factors", k: int, seed: int, q: int, response: str, refactor: bool):
+        self.f = f
+        self.k = k
+        self.Q = f.empty_block(k)
+        self.Z = f.empty_block(k)
+        self.sigma_B = torch.empty((f.n_omega, k), dtype=torch.float64, device="cuda")
+        self.sigma_AV = (torch.empty((f.n_omega, k), dtype=torch.float64, device="cuda")
+                         if response == "av" else None)
+        self.V = f.empty_block(k)
+        self.U = f.empty_block(k) if response in ("av", "qu") else None
+        self._g = ctypes.c_void_p()
+        check(lib().rr_graph_capture(f.handle, int(refactor), k, seed, q, RESPONSES[response],
+                                     _ptr(self.Q), _ptr(self.Z), _ptr(self.sigma_B),
+                                     _ptr(self.sigma_AV), _ptr(self.V), _ptr(self.U),
+                                     ctypes.byref(self._g)))
+
+    def launch(self, stream=None):
+        check(lib().rr_graph_launch(self._g, ctypes.c_void_p(_stream(stream))))
+        return {"sigma_B": self.sigma_B, "sigma_AV": self.sigma_AV, "V": self.V, "U": self.U,
+                "Q": self.Q}
+
+    def free(self):
+        if self._g:
+            lib().rr_graph_free(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def capture(f: Factors, k: int, seed: int = 0, q: int = 0, response: str = "av",
+            refactor: bool = True) -> Graph:
+    """Record one pass of Algorithm 1 (optionally with the refactorisation) for
+    replay with one graph launch."""
+    return Graph(f, k, seed, q, response, refactor)
+
+
+def factor_bytes(nx: int, ny: int, n_omega: int, k_max: int, precision: str = "fp64",
+                 tile: int = 0) -> int:
+    return int(lib().rr_factor_bytes(nx, ny, n_omega, k_max, PRECISIONS[precision], tile))
+
+
+def autotune(prob: BurgersProblem, omegas, k: int, precision: str = "fp64",
+             max_shifts: int = 0, stream=None) -> dict:
+    """The library's autotuner (rr_autotune): fastest band tile and persistent
+    grid for this operator, shift batch, width and precision."""
+    om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
+    re = np.ascontiguousarray(om.real)
+    im = np.ascontiguousarray(om.imag)
+    t = _lib.Tuning()
+    ms = ctypes.c_double()
+    ps = prob.c_struct()
+    check(lib().rr_autotune(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
+                            im.ctypes.data_as(ctypes.c_void_p), om.size, k,
+                            PRECISIONS[precision], max_shifts, ctypes.c_void_p(_stream(stream)),
+                            ctypes.byref(t), ctypes.byref(ms)))
+    return {"tile": t.tile, "grid": t.grid, "ms": ms.value}
+
+
+def sweep(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
+          precision: str = "fp64", tune: Optional[dict] = None, chunk: int = 0,
+          memory_fraction: float = 0.8) -> dict:
+    """Frequency sweep sharing one L: the shifts are processed in chunks that
+    fit in device memory (rr_factor_bytes), each chunk as one captured graph
+    (factorisation, sketch, subspace iteration, adjoint solve, SVD, eq. 9).
+    Returns sigma_B, sigma_AV (n_omega, k) on the GPU and the chunk size."""
+    om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
+    tile = int(tune["tile"]) if tune else 0
+    grid = int(tune["grid"]) if tune else 0
+    if chunk <= 0:
+        free, _ = torch.cuda.mem_get_info()
+        per = factor_bytes(prob.nx, prob.ny, 1, k, precision, tile) + 6 * k * prob.n * 16
+        chunk = max(1, min(om.size, int(memory_fraction * free // per)))
+    sB = torch.empty((om.size, k), dtype=torch.float64, device="cuda")
+    sAV = torch.empty((om.size, k), dtype=torch.float64, device="cuda")
+    for c0 in range(0, om.size, chunk):
+        f = factor(prob, om[c0:c0 + chunk], precision, k_max=k, tile=tile, grid=grid)
+        g = capture(f, k, seed, q, "av", refactor=False)
+        out = g.launch()
+        f.check()
+        sB[c0:c0 + chunk] = out["sigma_B"]
+        sAV[c0:c0 + chunk] = out["sigma_AV"]
+        g.free()
+        f.free()
+    return {"sigma_B": sB, "sigma_AV": sAV, "chunk": chunk}
+
+
 def factor(prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32, **kw) -> Factors:
     return Factors(prob, omegas, precision, k_max, **kw)
 

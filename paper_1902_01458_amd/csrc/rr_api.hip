@@ -121,6 +121,48 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
   return RR_OK;
 }
 
+// Device allocations of a handle, in one place for rr_factor and rr_factor_bytes.
+struct Plan {
+  BandGeom geom;
+  size_t coef, phi, U, omega, tiles, xs, flags, ctrl, theta, vec, work3, partial, kk2, grad;
+  int nchunk, grad_nchunk;
+  size_t nflags;
+  size_t total() const {
+    return coef + phi + U + omega + tiles + xs + flags + ctrl + theta + 2 * vec + work3 + partial +
+           5 * kk2 + grad;
+  }
+};
+
+Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T, bool has_phi,
+               bool has_U) {
+  Plan pl{};
+  const int64_t n = 2 * (int64_t)nx * ny;
+  const size_t nn = (size_t)nx * ny;
+  pl.geom.T = T;
+  pl.geom.B = (2 * ny + T - 1) / T;
+  pl.geom.NB = (int)((n + T - 1) / T);
+  const size_t elem = prec == RR_MIXED ? 2 * sizeof(float) : 2 * sizeof(double);
+  pl.coef = nn * 12 * sizeof(double);
+  pl.phi = has_phi ? nn * sizeof(double) : 0;
+  pl.U = has_U ? (size_t)(nx + 2) * (ny + 2) * sizeof(double) : 0;
+  pl.omega = 2 * (size_t)n_omega * sizeof(double);
+  pl.tiles = (size_t)n_omega * pl.geom.tiles_per_omega() * T * T * elem;
+  pl.xs = (size_t)n_omega * pl.geom.NB * T * solve_np(k_max) * 2 * sizeof(double);
+  pl.nflags = std::max((size_t)n_omega * pl.geom.tiles_per_omega(), (size_t)n_omega * pl.geom.NB);
+  pl.flags = pl.nflags * sizeof(int);
+  pl.ctrl = 64 * sizeof(uint32_t);
+  pl.theta = (size_t)k_max * n * 2 * sizeof(double);
+  pl.vec = (size_t)n_omega * k_max * n * 2 * sizeof(double);
+  pl.work3 = prec == RR_MIXED ? pl.vec : 0;
+  pl.nchunk = (int)((n + 2047) / 2048);
+  const size_t kk = (size_t)std::max(k_max * k_max, 64);
+  pl.partial = (size_t)n_omega * pl.nchunk * kk * 2 * sizeof(double);
+  pl.kk2 = (size_t)n_omega * kk * 2 * sizeof(double);
+  pl.grad_nchunk = (int)((nn + 255) / 256);
+  pl.grad = (size_t)n_omega * pl.grad_nchunk * 2 * sizeof(double);
+  return pl;
+}
+
 rr_status check_k(const rr_factors* f, int k) {
   if (!f) return fail(RR_ERR_INVALID, "NULL handle");
   if (f->sticky_hip_error) return fail(RR_ERR_HIP, "handle is unusable after a HIP error");
@@ -214,41 +256,38 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   }
   hipStream_t s = (hipStream_t)stream;
   const size_t nn = (size_t)p->nx * p->ny;
-  const size_t vec = (size_t)n_omega * k_max * f->n * 2 * sizeof(double);
-  const size_t elem = prec == RR_MIXED ? 2 * sizeof(float) : 2 * sizeof(double);
-  f->tile_bytes = (size_t)n_omega * f->geom.tiles_per_omega() * T * T * elem;
-  size_t nflags = std::max((size_t)n_omega * f->geom.tiles_per_omega(), (size_t)n_omega * f->geom.NB);
-  int nchunk = (f->n + 2047) / 2048;
-  size_t kk = (size_t)std::max(k_max * k_max, 64);
+  const Plan pl = make_plan(p->nx, p->ny, n_omega, k_max, prec, T, p->phi != nullptr,
+                            p->U != nullptr);
+  f->tile_bytes = pl.tiles;
   rr_status st = RR_OK;
 #define ALLOC(ptr, bytes)                      \
   do {                                         \
     st = dalloc(f, &(ptr), (bytes));           \
     if (st != RR_OK) goto fail_free;           \
   } while (0)
-  ALLOC(f->coef, nn * 12 * sizeof(double));
-  if (p->phi) ALLOC(f->phi, nn * sizeof(double));
-  if (p->U) ALLOC(f->U, (size_t)(p->nx + 2) * (p->ny + 2) * sizeof(double));
-  ALLOC(f->omega, 2 * n_omega * sizeof(double));
-  ALLOC(f->tiles, f->tile_bytes);
-  ALLOC(f->xs, (size_t)n_omega * f->geom.NB * T * solve_np(k_max) * 2 * sizeof(double));
-  ALLOC(f->flags, nflags * sizeof(int));
-  f->flag_count = nflags;
-  ALLOC(f->ctrl, 64 * sizeof(uint32_t));
-  ALLOC(f->theta, (size_t)k_max * f->n * 2 * sizeof(double));
-  ALLOC(f->work1, vec);
-  ALLOC(f->work2, vec);
-  if (prec == RR_MIXED) ALLOC(f->work3, vec);
-  ALLOC(f->small.partial, (size_t)n_omega * nchunk * kk * 2 * sizeof(double));
-  ALLOC(f->small.G, (size_t)n_omega * kk * 2 * sizeof(double));
-  ALLOC(f->small.R, (size_t)n_omega * kk * 2 * sizeof(double));
-  ALLOC(f->small.Rinv, (size_t)n_omega * kk * 2 * sizeof(double));
-  ALLOC(f->small.W, (size_t)n_omega * kk * 2 * sizeof(double));
-  ALLOC(f->small.Ut, (size_t)n_omega * kk * 2 * sizeof(double));
-  f->small.nchunk = nchunk;
+  ALLOC(f->coef, pl.coef);
+  if (p->phi) ALLOC(f->phi, pl.phi);
+  if (p->U) ALLOC(f->U, pl.U);
+  ALLOC(f->omega, pl.omega);
+  ALLOC(f->tiles, pl.tiles);
+  ALLOC(f->xs, pl.xs);
+  ALLOC(f->flags, pl.flags);
+  f->flag_count = pl.nflags;
+  ALLOC(f->ctrl, pl.ctrl);
+  ALLOC(f->theta, pl.theta);
+  ALLOC(f->work1, pl.vec);
+  ALLOC(f->work2, pl.vec);
+  if (prec == RR_MIXED) ALLOC(f->work3, pl.work3);
+  ALLOC(f->small.partial, pl.partial);
+  ALLOC(f->small.G, pl.kk2);
+  ALLOC(f->small.R, pl.kk2);
+  ALLOC(f->small.Rinv, pl.kk2);
+  ALLOC(f->small.W, pl.kk2);
+  ALLOC(f->small.Ut, pl.kk2);
+  f->small.nchunk = pl.nchunk;
   f->small.kmax = k_max;
-  f->grad_nchunk = (int)((nn + 255) / 256);
-  ALLOC(f->grad_partial, (size_t)n_omega * f->grad_nchunk * 2 * sizeof(double));
+  f->grad_nchunk = pl.grad_nchunk;
+  ALLOC(f->grad_partial, pl.grad);
 #undef ALLOC
   {
     hipError_t e = hipMemcpyAsync(f->coef, p->coef, nn * 12 * sizeof(double),
@@ -276,6 +315,14 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
     f->hy = (p->y1 - p->y0) / (p->ny + 1);
     f->nu = p->nu;
     f->has_burgers = true;
+  }
+  {
+    hipError_t e = prepare_factor(T, prec == RR_MIXED);
+    if (e == hipSuccess) e = prepare_solve(T, prec == RR_MIXED);
+    if (e != hipSuccess) {
+      st = fail(RR_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(e));
+      goto fail_free;
+    }
   }
   st = rr_refactor(f, stream);
   if (st != RR_OK) goto fail_free;
@@ -422,6 +469,147 @@ void rr_factors_free(rr_factors* f) {
   (void)hipDeviceSynchronize();
   free_all(f);
   delete f;
+}
+
+size_t rr_factor_bytes(int32_t nx, int32_t ny, int32_t n_omega, int32_t k_max, rr_precision prec,
+                       int32_t tile) {
+  if (nx < 1 || ny < 1 || n_omega < 1 || k_max < 1 || k_max > 32) return 0;
+  const int T = tile ? tile : 64;
+  if (T != 32 && T != 64) return 0;
+  return make_plan(nx, ny, n_omega, k_max, prec, T, true, true).total();
+}
+
+// ---------------------------------------------------------------------------
+// Captured sweeps
+// ---------------------------------------------------------------------------
+struct rr_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void rr_graph_free(rr_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+rr_status rr_graph_capture(rr_factors* f, int32_t refactor, int32_t k, uint64_t seed, int32_t q,
+                           rr_response mode, double* Q, double* Z, double* sigma_B,
+                           double* sigma_AV, double* V, double* Uresp, rr_graph** out) {
+  if (!out) return fail(RR_ERR_INVALID, "NULL output graph pointer");
+  *out = nullptr;
+  rr_status st = check_k(f, k);
+  if (st != RR_OK) return st;
+  if (!Q || !Z || !sigma_B || !V) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (Q == Z) return fail(RR_ERR_INVALID, "Z may not alias Q");
+  // Capture on a private stream (the legacy default stream cannot capture);
+  // replays are ordered on whatever stream rr_graph_launch is given.
+  hipStream_t cs = nullptr;
+  RR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(RR_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  if (refactor) st = rr_refactor(f, cs);
+  if (st == RR_OK) st = rr_sketch_solve(f, k, seed, q, Q, cs);
+  if (st == RR_OK) st = rr_adjoint_solve(f, k, Q, Z, cs);
+  if (st == RR_OK) st = rr_gains(f, k, Q, Z, mode, sigma_B, sigma_AV, V, Uresp, cs);
+  rr_graph* g = new rr_graph();
+  e = hipStreamEndCapture(cs, &g->graph);
+  (void)hipStreamDestroy(cs);
+  if (st == RR_OK && e != hipSuccess)
+    st = fail(RR_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  if (st == RR_OK) {
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+      st = fail(RR_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  if (st != RR_OK) {
+    rr_graph_free(g);
+    return st;
+  }
+  *out = g;
+  return RR_OK;
+}
+
+rr_status rr_graph_launch(rr_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(RR_ERR_INVALID, "NULL graph");
+  RR_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return RR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double* omega_im,
+                      int32_t n_omega, int32_t k, rr_precision prec, int32_t max_shifts,
+                      void* stream, rr_tuning* out, double* out_ms) {
+  if (!p || !omega_re || !out) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (n_omega < 1 || k < 1 || k > 32) return fail(RR_ERR_INVALID, "bad n_omega or k");
+  const int nw = (max_shifts > 0 && max_shifts < n_omega) ? max_shifts : n_omega;
+  const int64_t n = 2 * (int64_t)p->nx * p->ny;
+  hipStream_t s = (hipStream_t)stream;
+  const int cus = device_cus();
+  const int tiles[2] = {64, 32};
+  const int grids[2] = {cus, 2 * cus};
+  double best = -1.0;
+  rr_tuning pick{};
+  double *Q = nullptr, *Z = nullptr;
+  const size_t vb = (size_t)nw * k * n * 2 * sizeof(double);
+  if (hipMalloc((void**)&Q, vb) != hipSuccess || hipMalloc((void**)&Z, vb) != hipSuccess) {
+    (void)hipGetLastError();
+    if (Q) (void)hipFree(Q);
+    return fail(RR_ERR_NOMEM, "autotune: no room for the trial blocks");
+  }
+  hipEvent_t ev[4];
+  for (auto& x : ev) (void)hipEventCreate(&x);
+  rr_status st = RR_OK;
+  for (int ti = 0; ti < 2 && st == RR_OK; ti++) {
+    for (int gi = 0; gi < 2 && st == RR_OK; gi++) {
+      rr_tuning t{tiles[ti], grids[gi], 0, 0.0, 0.0};
+      rr_factors* h = nullptr;
+      rr_status fs = rr_factor(p, omega_re, omega_im, nw, k, prec, &t, stream, &h);
+      if (fs == RR_ERR_NOMEM) continue;  // this candidate does not fit
+      if (fs != RR_OK) { st = fs; break; }
+      // warm-up pass, then one timed pass: factor, sketch solve, adjoint solve
+      fs = rr_sketch_solve(h, k, 0, 0, Q, stream);
+      if (fs == RR_OK) fs = rr_adjoint_solve(h, k, Q, Z, stream);
+      if (fs == RR_OK) fs = rr_check(h, stream);
+      float ms_f = 0, ms_s = 0, ms_a = 0;
+      if (fs == RR_OK) {
+        (void)hipEventRecord(ev[0], s);
+        fs = rr_refactor(h, stream);
+        (void)hipEventRecord(ev[1], s);
+        if (fs == RR_OK) fs = rr_sketch_solve(h, k, 0, 0, Q, stream);
+        (void)hipEventRecord(ev[2], s);
+        if (fs == RR_OK) fs = rr_adjoint_solve(h, k, Q, Z, stream);
+        (void)hipEventRecord(ev[3], s);
+        if (fs == RR_OK) fs = rr_check(h, stream);
+        (void)hipEventElapsedTime(&ms_f, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&ms_s, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&ms_a, ev[2], ev[3]);
+      }
+      rr_factors_free(h);
+      if (fs != RR_OK) { st = fs; break; }
+      // one pass of Algorithm 1 with a subspace iteration costs a factor and
+      // about five solves (sketch, two iteration solves, adjoint, recovery)
+      const double score = ms_f + 2.5 * (ms_s + ms_a);
+      if (best < 0 || score < best) {
+        best = score;
+        pick = t;
+      }
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  (void)hipFree(Q);
+  (void)hipFree(Z);
+  if (st != RR_OK) return st;
+  if (best < 0) return fail(RR_ERR_NOMEM, "autotune: no candidate fits in device memory");
+  *out = pick;
+  if (out_ms) *out_ms = best;
+  return RR_OK;
 }
 
 }  // extern "C"

@@ -686,13 +686,31 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
 }
 
 template <typename R, int T>
+constexpr size_t factor_lds() {
+  return sizeof(cplx<R>) * ((size_t)T * FGeom<T>::LDT + (size_t)T * T / 2);
+}
+
+template <typename R, int T>
 static hipError_t launch_factor_t(const FactorParams& P, int grid, hipStream_t s) {
-  size_t lds = sizeof(cplx<R>) * ((size_t)T * FGeom<T>::LDT + (size_t)T * T / 2);
-  hipError_t e = hipFuncSetAttribute((const void*)k_factor<R, T>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  const size_t lds = factor_lds<R, T>();
   hipLaunchKernelGGL((k_factor<R, T>), dim3(grid), dim3(FGeom<T>::NT), lds, s, P);
   return hipGetLastError();
+}
+
+// Dynamic-LDS limit of the factor kernel (a host call, kept out of the launch
+// path so that launches can be captured into a graph).
+hipError_t prepare_factor(int T, bool fp32) {
+  auto set = [](const void* fn, size_t lds) {
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  };
+  if (fp32) {
+    if (T == 64) return set((const void*)k_factor<float, 64>, factor_lds<float, 64>());
+    if (T == 32) return set((const void*)k_factor<float, 32>, factor_lds<float, 32>());
+  } else {
+    if (T == 64) return set((const void*)k_factor<double, 64>, factor_lds<double, 64>());
+    if (T == 32) return set((const void*)k_factor<double, 32>, factor_lds<double, 32>());
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega, int n_omega,

@@ -113,6 +113,10 @@ hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t se
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega,
                          int n_omega, bool fp32, void* tiles, int* flags, uint32_t* ticket,
                          uint32_t* status, int grid, hipStream_t s);
+// Dynamic-LDS attributes of the factor / solve kernels for one tile and
+// precision; called when a handle is created, never on the launch path.
+hipError_t prepare_factor(int T, bool fp32);
+hipError_t prepare_solve(int T, bool fp32);
 // Multi-RHS solve with the band factor: X = M^-1 Bm (adjoint: M^-H Bm).
 // Bm's blocks are bstride complex elements apart (0: shared); Bm may alias X.
 // xs: workspace of n_omega * NB * T * solve_np(k) complex (FP64 size).

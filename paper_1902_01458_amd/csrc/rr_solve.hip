@@ -264,12 +264,31 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
 template <typename R, int T, int NP, bool ADJ>
 static hipError_t launch_a(const Solve2Params& P, int grid, hipStream_t s) {
   size_t lds = sizeof(cplx<R>) * (size_t)T * NP;
-  hipError_t e = hipFuncSetAttribute((const void*)k_solve2<R, T, NP, ADJ>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_solve2<R, T, NP, ADJ>), dim3(grid), dim3(64 * (T / 16) * (NP / 16)), lds,
                      s, P);
   return hipGetLastError();
+}
+
+template <typename R, int T>
+static hipError_t prepare_t() {
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* fn, int np) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(cplx<R>) * T * np));
+  };
+  set((const void*)k_solve2<R, T, 16, false>, 16);
+  set((const void*)k_solve2<R, T, 16, true>, 16);
+  set((const void*)k_solve2<R, T, 32, false>, 32);
+  set((const void*)k_solve2<R, T, 32, true>, 32);
+  return e;
+}
+
+// Dynamic-LDS limits of the solve kernels of one tile / precision (host
+// calls, kept out of the launch path so that launches can be captured).
+hipError_t prepare_solve(int T, bool fp32) {
+  if (fp32) return T == 64 ? prepare_t<float, 64>() : prepare_t<float, 32>();
+  return T == 64 ? prepare_t<double, 64>() : prepare_t<double, 32>();
 }
 
 template <typename R, int T, int NP>
@@ -282,8 +301,6 @@ static hipError_t launch_np(const Solve2Params& P, int NP, int grid, hipStream_t
   switch (NP) {
     case 16: return launch_t<R, T, 16>(P, grid, s);
     case 32: return launch_t<R, T, 32>(P, grid, s);
-    case 48: return launch_t<R, T, 48>(P, grid, s);
-    case 64: return launch_t<R, T, 64>(P, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -295,7 +312,7 @@ hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
                         int grid, hipStream_t s, const uint32_t* skip) {
   int NP = solve_np(k);
-  if (NP > 64 || (g.T == 64 && NP > 64) || (g.T * NP > 64 * 64)) return hipErrorInvalidValue;
+  if (NP > 32) return hipErrorInvalidValue;  // k <= 32 (rr_factor's k_max bound)
   Solve2Params P{g, n, n_omega, k, adjoint, tiles, (const double2*)Bm, bstride, (double2*)X,
                  xs, flags, ticket, status, (int64_t)n_omega * 2 * g.NB, skip};
   hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.NB, s);
