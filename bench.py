@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1_batch16")
-    ap.add_argument("--tile", type=int, default=64)
+    ap.add_argument("--tile", type=int, default=64,
+                    help="band tile when --no-autotune is given")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--refine-iters", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -47,33 +50,43 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(prob, w, precision, steps, warmup, tile, refine_iters):
+def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, graph_reps):
     import torch
 
     import paper_1902_01458_amd as rr
-    f = rr.factor(prob, list(w.omegas), precision, k_max=w.k, tile=tile,
-                  refine_iters=refine_iters)
+    tune = {"tile": tile, "grid": 0, "ms": None}
+    if autotune:
+        tune = rr.autotune(prob, list(w.omegas), w.k, precision)
+    f = rr.factor(prob, list(w.omegas), precision, k_max=w.k, tile=tune["tile"],
+                  grid=tune["grid"], refine_iters=refine_iters)
     f.check()
     stream = torch.cuda.current_stream()
     Q = f.empty_block(w.k)
     Z = f.empty_block(w.k)
     outs = {}
+    names = ("factor", "sketch", "adjoint", "gains")
 
     def step(ev=None):
+        # ev: 5 events bracketing the four calls, recorded on the launch stream
         if ev is not None:
             ev[0].record(stream)
         f.refactor()
         if ev is not None:
             ev[1].record(stream)
         f.sketch_solve(w.k, w.seed, w.q, out=Q)
+        if ev is not None:
+            ev[2].record(stream)
         f.adjoint_solve(Q, out=Z)
+        if ev is not None:
+            ev[3].record(stream)
         outs.update(f.gains(Q, Z, "av", out=outs))
+        if ev is not None:
+            ev[4].record(stream)
 
     for _ in range(warmup):
         step()
     f.check()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -81,14 +94,49 @@ def run_path(prob, w, precision, steps, warmup, tile, refine_iters):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     f.check()
-    factor_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "factor_ms": factor_ms,
+    per = {nm: float(np.mean([e[c].elapsed_time(e[c + 1]) for e in evs]))
+           for c, nm in enumerate(names)}
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "factor_ms": per["factor"], "calls_ms": per,
            "sigma_B": outs["sigma_B"].cpu().numpy(), "sigma_AV": outs["sigma_AV"].cpu().numpy(),
-           "refine": f.refine_count(), "bytes": f.nbytes()}
+           "refine": f.refine_count(), "bytes": f.nbytes(), "tune": tune}
+    if graph_reps > 0:
+        # the same pass captured once and replayed (outside the timed region)
+        g = rr.capture(f, w.k, w.seed, w.q, "av", refactor=True)
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(graph_reps):
+            g.launch()
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / graph_reps
+        f.check()
+        res["graph_sigma_equal"] = bool(np.array_equal(g.sigma_B.cpu().numpy(), res["sigma_B"]))
+        g.free()
     f.free()
     del Q, Z, outs
     torch.cuda.empty_cache()
     return res
+
+
+TRAFFIC = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+CSRC = os.path.join(ROOT, "paper_1902_01458_amd", "csrc")
+
+
+def traffic(kernel):
+    """HBM bytes per launch of `kernel` from the calibrated FETCH_SIZE / WRITE_SIZE
+    counters recorded in profiles/pmc_traffic.json, or None when none were taken
+    or the kernel sources changed since (the file keeps their SHA-256)."""
+    import hashlib
+    if not os.path.exists(TRAFFIC):
+        return None
+    rec = json.load(open(TRAFFIC))
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        h.update(open(os.path.join(CSRC, fn), "rb").read())
+    if rec.get("sources_sha256") != h.hexdigest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
 def accuracy(res, gold):
@@ -110,7 +158,9 @@ def cpu_baseline(w, shifts):
     phi = osk.gradient_weight(U, hx, hy).ravel()
     Om = osk.test_matrix(w.n, w.k, phi, w.seed)
     cores = os.cpu_count() or 1
-    sel = [w.omegas[6]] if shifts == 1 else list(w.omegas[:shifts])  # 6 -> omega = 2.0
+    # one shift: omega = 2.0, the single frequency of the 512 x 256 configuration
+    i2 = int(np.argmin(np.abs(np.asarray(w.omegas) - 2.0)))
+    sel = [w.omegas[i2]] if shifts == 1 else list(w.omegas[:shifts])
     with threadpoolctl.threadpool_limits(cores):
         t0 = time.perf_counter()
         for om in sel:
@@ -144,18 +194,25 @@ def main():
     gold = json.load(open(GOLDEN)) if (os.path.exists(GOLDEN) and args.workload == "cfg1_batch16") \
         else None
     b = 2 * w.ny
-    flops = 8.0 * w.n * b * b * len(w.omegas)  # algorithmic band-LU flops per launch
-    mixed = run_path(prob, w, "mixed", args.steps, args.warmup, args.tile, args.refine_iters)
-    print(f"# mixed: {mixed['ms_per_step']:.1f} ms/step, factor {mixed['factor_ms']:.1f} ms, "
-          f"refine {mixed['refine']}", file=sys.stderr, flush=True)
+    n_om = len(w.omegas)
+    flops = 8.0 * w.n * b * b * n_om  # algorithmic band-LU flops per launch (all shifts)
+    # algorithmic bytes of one FP64 solve launch: the factors once (n (2b+1)
+    # complex entries per shift), the right-hand sides in and the solutions out
+    solve_bytes = n_om * (w.n * (2 * b + 1) * 16 + 2 * w.k * w.n * 16)
+    auto = not args.no_autotune
+    mixed = run_path(prob, w, "mixed", args.steps, args.warmup, args.tile, args.refine_iters,
+                     auto, args.graph_reps)
+    print(f"# mixed: {mixed['ms_per_step']:.1f} ms/step {mixed['calls_ms']}, refine "
+          f"{mixed['refine']}, tune {mixed['tune']}", file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:
-        fp64 = run_path(prob, w, "fp64", args.steps, args.warmup, args.tile, 0)
-        print(f"# fp64: {fp64['ms_per_step']:.1f} ms/step, factor {fp64['factor_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
-    n_om = len(w.omegas)
+        fp64 = run_path(prob, w, "fp64", args.steps, args.warmup, args.tile, 0, auto,
+                        args.graph_reps)
+        print(f"# fp64: {fp64['ms_per_step']:.1f} ms/step {fp64['calls_ms']}, tune "
+              f"{fp64['tune']}", file=sys.stderr, flush=True)
     value = n_om / (mixed["ms_per_step"] * 1e-3)
     ach = flops / (mixed["factor_ms"] * 1e-3) / 1e12
+    fk = f"k_factor<float,{mixed['tune']['tile']}>"
     line = {
         "metric": METRIC, "value": value, "unit": "ω-solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
@@ -164,21 +221,35 @@ def main():
         "config": {"workload": f"{args.workload}: 2-D linearised Burgers {w.nx}x{w.ny}, n={w.n}, "
                                f"half-bandwidth {b}, {n_om} shifts 0.25..8, k={w.k}, q={w.q}, "
                                "Phi-weighted Gaussian sketch, seed 0",
-                   "tile": args.tile},
+                   "tile": mixed["tune"]["tile"], "grid": mixed["tune"]["grid"],
+                   "autotuned": auto},
         "gains_per_s": value * w.k,
         "sigma1_rel_err_vs_oracle": accuracy(mixed, gold),
         "refine_corrections": mixed["refine"],
+        "calls_ms": mixed["calls_ms"],
+        "graph_ms_per_step": mixed.get("graph_ms_per_step"),
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK["mixed"], "unit": "TFLOP/s",
-                     "frac": ach / PEAK["mixed"], "traffic": None,
-                     "kernel": "k_factor<float,64> (band LU, 16 shifts per launch)",
-                     "factor_ms": mixed["factor_ms"]},
+                     "frac": ach / PEAK["mixed"], "traffic": traffic(fk),
+                     "kernel": f"{fk} (band LU of all {n_om} shifts, one launch)",
+                     "launch_ms": mixed["factor_ms"]},
     }
     if fp64 is not None:
         a64 = flops / (fp64["factor_ms"] * 1e-3) / 1e12
+        sk = f"k_solve2<double,{fp64['tune']['tile']},32,true>"
+        bw = solve_bytes / (fp64["calls_ms"]["adjoint"] * 1e-3) / 1e9
         line["fp64"] = {"value": n_om / (fp64["ms_per_step"] * 1e-3),
-                        "ms_per_step": fp64["ms_per_step"], "factor_ms": fp64["factor_ms"],
+                        "ms_per_step": fp64["ms_per_step"], "calls_ms": fp64["calls_ms"],
+                        "graph_ms_per_step": fp64.get("graph_ms_per_step"),
+                        "tile": fp64["tune"]["tile"], "grid": fp64["tune"]["grid"],
                         "sigma1_rel_err_vs_oracle": accuracy(fp64, gold),
-                        "factor_tflops": a64, "factor_frac": a64 / PEAK["fp64"]}
+                        "factor_roofline": {"bound": "mfma", "achieved": a64,
+                                            "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                                            "frac": a64 / PEAK["fp64"]}}
+        line["roofline_solve"] = {"bound": "hbm", "achieved": bw, "peak": 8000.0, "unit": "GB/s",
+                                  "frac": bw / 8000.0, "traffic": traffic(sk),
+                                  "kernel": f"{sk} (adjoint solve, FP64, all {n_om} shifts x "
+                                            f"{w.k} columns, one launch)",
+                                  "launch_ms": fp64["calls_ms"]["adjoint"]}
         line["mixed_over_fp64"] = line["fp64"]["ms_per_step"] / mixed["ms_per_step"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_shifts)
