@@ -45,7 +45,9 @@
  *     After an error the contents of the outputs are unspecified.
  *   - A handle is not thread-safe; distinct handles are independent.
  *   - No call allocates device memory except rr_factor (which sizes every
- *     workspace for k <= k_max) and rr_autotune (trial handles), and no
+ *     workspace for k <= k_max, through rr_set_allocator's allocator if one
+ *     is registered), rr_autotune (trial handles) and the test helper
+ *     rr_apply (a shift buffer; it synchronises), and no
  *     launch path makes a host-side runtime call, so the sequence refactor /
  *     sketch_solve / adjoint_solve / gains / grad can be captured into a HIP
  *     graph (rr_graph_capture does so for one pass of Algorithm 1).
@@ -140,7 +142,8 @@ rr_status rr_burgers_coeffs(int32_t nx, int32_t ny, const double* U, double x0, 
 /* Apply the shifted operator: Y = M(omega_w) X for every shift w (FP64, from
  * the stencil; used for residuals and tests).  X, Y: device (n_omega, k, n)
  * complex.  omega_re/omega_im: host, n_omega each (omega_im may be NULL).
- * adjoint != 0 applies M^H instead. */
+ * adjoint != 0 applies M^H instead.  Allocates a small shift buffer and
+ * synchronises `stream` before returning. */
 rr_status rr_apply(const rr_problem* p, const double* omega_re, const double* omega_im,
                    int32_t n_omega, int32_t k, int32_t adjoint, const double* X, double* Y,
                    void* stream);
@@ -213,6 +216,17 @@ size_t rr_bytes(const rr_factors* f);
 
 /* Free a handle (NULL-safe). Synchronises the device first. */
 void rr_factors_free(rr_factors* f);
+
+/* Device allocator for the handles created after this call (process-wide):
+ * alloc(bytes, stream, ctx) returns device memory or NULL, dealloc(ptr, ctx)
+ * returns it; NULL, NULL restores hipMalloc / hipFree.  This lets a
+ * framework's caching allocator (PyTorch's) own the factors and workspaces.
+ * `stream` is the one given to rr_factor; a handle frees through the
+ * allocator that created it, after synchronising the device.  Returns
+ * RR_ERR_INVALID if exactly one of the two is NULL. */
+typedef void* (*rr_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*rr_free_fn)(void* ptr, void* ctx);
+rr_status rr_set_allocator(rr_alloc_fn alloc, rr_free_fn dealloc, void* ctx);
 
 /* Device bytes rr_factor would allocate for these sizes (with phi and U),
  * 0 for invalid sizes; tile 0 means the default.  A sweep too large for the

@@ -9,10 +9,11 @@ sweeps and the gradient of the leading gain.  All numerical work runs in the
 HIP kernels of librr.so; this package only marshals arguments.
 """
 from .api import (BurgersProblem, Factors, Graph, autotune, capture, factor,  # noqa: F401
-                  factor_bytes, philox_raw, resolvent, sketch, sweep)
+                  factor_bytes, philox_raw, resolvent, sketch, sweep, use_torch_allocator)
 from ._lib import RRError, lib  # noqa: F401
 from .autograd import SigmaOne, sigma_one  # noqa: F401
 
 __all__ = ["BurgersProblem", "Factors", "Graph", "factor", "resolvent", "sketch", "philox_raw",
-           "capture", "autotune", "sweep", "factor_bytes", "RRError", "lib", "SigmaOne",
+           "capture", "autotune", "sweep", "factor_bytes", "use_torch_allocator", "RRError", "lib",
+           "SigmaOne",
            "sigma_one"]

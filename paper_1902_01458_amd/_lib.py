@@ -17,7 +17,7 @@ RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
 # every symbol include/rr.h declares, plus the two test hooks of rr_operator.hip
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
            "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_grad", "rr_check", "rr_refine_count",
-           "rr_bytes", "rr_factors_free", "rr_factor_bytes", "rr_graph_capture",
+           "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
            "rr_sketch")
 
@@ -33,6 +33,10 @@ class Problem(ctypes.Structure):
                 ("coef", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("U", ctypes.c_void_p),
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
                 ("y1", ctypes.c_double), ("nu", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Tuning(ctypes.Structure):
@@ -76,6 +80,7 @@ def lib() -> ctypes.CDLL:
                           ctypes.c_uint32, vp],
         "rr_sketch": [pp, i32, u64, vp, vp],
         "rr_factor_bytes": [i32, i32, i32, i32, ctypes.c_int, i32],
+        "rr_set_allocator": [ALLOC_FN, FREE_FN, vp],
         "rr_graph_capture": [vp, i32, i32, u64, i32, ctypes.c_int, vp, vp, vp, vp, vp, vp,
                              ctypes.POINTER(vp)],
         "rr_graph_launch": [vp, vp],

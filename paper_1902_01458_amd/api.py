@@ -263,6 +263,32 @@ def capture(f: Factors, k: int, seed: int = 0, q: int = 0, response: str = "av",
     return Graph(f, k, seed, q, response, refactor)
 
 
+_ALLOCATOR = None  # the registered ctypes callbacks (kept alive here)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the device memory of new handles through PyTorch's caching
+    allocator (rr_set_allocator), or back to hipMalloc / hipFree."""
+    global _ALLOCATOR
+    if not enable:
+        check(lib().rr_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None))
+        _ALLOCATOR = None
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream or 0)
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cbs = (_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free))
+    check(lib().rr_set_allocator(cbs[0], cbs[1], None))
+    _ALLOCATOR = cbs
+
+
 def factor_bytes(nx: int, ny: int, n_omega: int, k_max: int, precision: str = "fp64",
                  tile: int = 0) -> int:
     return int(lib().rr_factor_bytes(nx, ny, n_omega, k_max, PRECISIONS[precision], tile))

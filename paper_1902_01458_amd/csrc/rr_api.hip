@@ -47,14 +47,25 @@ bool is_dev_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// Process-wide device allocator for new handles (rr_set_allocator); each
+// handle keeps the one it was created with.
+rr_alloc_fn g_alloc = nullptr;
+rr_free_fn g_dealloc = nullptr;
+void* g_alloc_ctx = nullptr;
+
 template <typename T>
 rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
   if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc((void**)p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(RR_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  if (f->alloc) {
+    *p = (T*)f->alloc(bytes, f->alloc_stream, f->alloc_ctx);
+    if (!*p) return fail(RR_ERR_NOMEM, "allocator returned NULL for " + std::to_string(bytes));
+  } else {
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(RR_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
   }
   f->bytes += bytes;
   return RR_OK;
@@ -64,8 +75,11 @@ void free_all(rr_factors* f) {
   void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->flags, f->ctrl, f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
                 f->small.Rinv, f->small.W, f->small.Ut, f->grad_partial};
-  for (void* p : ps)
-    if (p) (void)hipFree(p);
+  for (void* p : ps) {
+    if (!p) continue;
+    if (f->dealloc) f->dealloc(p, f->alloc_ctx);
+    else (void)hipFree(p);
+  }
 }
 
 OpDesc opdesc(const rr_factors* f) { return OpDesc{f->nx, f->ny, f->n, f->coef}; }
@@ -234,6 +248,10 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
     return fail(RR_ERR_INVALID, "coef/phi/U must be device pointers");
 
   rr_factors* f = new rr_factors();
+  f->alloc = g_alloc;
+  f->dealloc = g_dealloc;
+  f->alloc_ctx = g_alloc_ctx;
+  f->alloc_stream = stream;
   f->nx = p->nx;
   f->ny = p->ny;
   f->n = (int)n64;
@@ -469,6 +487,15 @@ void rr_factors_free(rr_factors* f) {
   (void)hipDeviceSynchronize();
   free_all(f);
   delete f;
+}
+
+rr_status rr_set_allocator(rr_alloc_fn alloc, rr_free_fn dealloc, void* ctx) {
+  if ((alloc == nullptr) != (dealloc == nullptr))
+    return fail(RR_ERR_INVALID, "alloc and dealloc must both be set or both be NULL");
+  g_alloc = alloc;
+  g_dealloc = dealloc;
+  g_alloc_ctx = ctx;
+  return RR_OK;
 }
 
 size_t rr_factor_bytes(int32_t nx, int32_t ny, int32_t n_omega, int32_t k_max, rr_precision prec,

@@ -197,6 +197,11 @@ struct rr_factors {
   double* grad_partial = nullptr;
   int grad_nchunk = 0;
   size_t bytes = 0;
+  // allocator the handle was created with (NULL: hipMalloc / hipFree)
+  rr_alloc_fn alloc = nullptr;
+  rr_free_fn dealloc = nullptr;
+  void* alloc_ctx = nullptr;
+  void* alloc_stream = nullptr;
   int refine_used = 0;
   bool sticky_hip_error = false;
 };

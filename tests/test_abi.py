@@ -71,3 +71,35 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "librr.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_sweep_entry_points_reject_bad_arguments_on_host():
+    L = _lib.lib()
+    g = ctypes.c_void_p()
+    assert L.rr_graph_capture(None, 1, 4, 0, 0, 0, None, None, None, None, None, None,
+                              ctypes.byref(g)) == 1
+    assert L.rr_graph_launch(None, None) == 1
+    L.rr_graph_free(None)  # NULL-safe
+    t = _lib.Tuning()
+    one = (ctypes.c_double * 1)(1.0)
+    assert L.rr_autotune(None, one, None, 1, 4, 0, 0, None, ctypes.byref(t), None) == 1
+    p = _lib.Problem(4, 4, 1, None, None, 0, 1, 0, 1, 0.01)
+    assert L.rr_autotune(ctypes.byref(p), one, None, 1, 33, 0, 0, None, ctypes.byref(t), None) == 1
+    # allocator: both callbacks or neither
+    assert L.rr_set_allocator(_lib.ALLOC_FN(lambda n, s, c: None), _lib.FREE_FN(), None) == 1
+    assert L.rr_set_allocator(_lib.ALLOC_FN(), _lib.FREE_FN(), None) == 0
+
+
+def test_factor_bytes_matches_the_layout():
+    L = _lib.lib()
+    assert L.rr_factor_bytes(0, 4, 1, 4, 0, 0) == 0
+    assert L.rr_factor_bytes(4, 4, 1, 33, 0, 0) == 0
+    assert L.rr_factor_bytes(4, 4, 1, 4, 0, 48) == 0
+    nx, ny, nw, k, T = 512, 256, 16, 20, 64
+    n, b = 2 * nx * ny, 2 * ny
+    B, NB = -(-b // T), -(-n // T)
+    tiles = nw * NB * (2 * B + 1 + 8) * T * T * 16  # band + chain tiles, complex FP64
+    got = L.rr_factor_bytes(nx, ny, nw, k, 0, T)
+    assert tiles < got < tiles * 1.2
+    # FP32 factor: half the tile bytes, one more vector workspace
+    assert L.rr_factor_bytes(nx, ny, nw, k, 1, T) < got

@@ -83,3 +83,28 @@ def test_cfg2_sweep_matches_oracle(prec, tol):
         r = ores.randomized_resolvent(L, w.omegas[i], Om, q=w.q)
         assert gain_errors(sB[i], r.sigma_B).max() <= tol, i
         assert gain_errors(sAV[i], r.sigma_AV).max() <= tol, i
+
+
+def test_torch_caching_allocator_owns_handle_memory():
+    """rr_set_allocator: a handle built through PyTorch's caching allocator
+    gives the same bits as one built with hipMalloc, its bytes show up in
+    torch's accounting, and they go back when the handle is freed."""
+    w = W.small("al", 30, 24, nu=1e-2, omegas=(0.5, 2.0), k=6, q=1)
+    prob = rr().BurgersProblem.from_workload(w)
+    ref = rr().resolvent(prob, list(w.omegas), k=w.k, q=w.q, tile=32)
+    ref_s = to_np(ref["sigma_B"])
+    ref["factors"].free()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    rr().use_torch_allocator(True)
+    try:
+        f = rr().factor(prob, list(w.omegas), "fp64", k_max=w.k, tile=32)
+        assert torch.cuda.memory_allocated() - before >= f.nbytes()
+        out = rr().resolvent(prob, list(w.omegas), k=w.k, q=w.q, factors=f)
+        np.testing.assert_array_equal(to_np(out["sigma_B"]), ref_s)
+        del out
+        f.free()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() <= before + 4096
+    finally:
+        rr().use_torch_allocator(False)
