@@ -32,11 +32,11 @@
 //
 // Chain tiles.  In each sweep of a solve, block s depends on the blocks t
 // within B of it through x_s = D^-1 (b_s - sum_t T_st x_t), D^-1 a triangle of
-// the diagonal inverse.  For the two nearest neighbours (distance d = 1, 2)
-// the factorisation stores the products G_s,d = D^-1 T_s,s-+d, so that a solve
-// step applies D^-1 to the far terms three or more blocks back, before either
-// neighbour is ready, and the two products left after that are register MFMAs
-// with no LDS round trip:  x_s = D^-1 (b_s - sum_far) - G_s,2 x_s-+2 - G_s,1 x_s-+1.
+// the diagonal inverse.  For the nearest neighbours (distance d = 1 .. 3) the
+// factorisation stores the products G_s,d = D^-1 T_s,s-+d, so that a solve
+// step applies D^-1 to the far terms, four or more blocks back, long before
+// the neighbours are ready, and every product left is a register MFMA with no
+// LDS round trip:  x_s = D^-1 (b_s - sum_far) - sum_{d <= 3} G_s,d x_s-+d.
 //   CH_FWD_L,d = L_ss^-1 L_s,s-d   (column-major)   forward, L sweep
 //   CH_FWD_U,d = U_ss^-1 U_s,s+d   (column-major)   forward, U sweep
 //   CH_ADJ_U,d = U_s-d,s U_ss^-1   (row-major)      adjoint, U^H sweep (used as ^H)
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     // 4. chain tiles (off the dependency chain: published data first)
     const int d = mx - m;
     if (r == t) {
-      for (int dd = 1; dd <= 2 && dd <= B && m - dd >= 0; dd++) {
+      for (int dd = 1; dd <= BandGeom::kChainD && dd <= B && m - dd >= 0; dd++) {
         // L_mm^-1 L_m,m-dd and U_m-dd,m U_mm^-1, with D still in LDS
         acc.zero();
         tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_UNIT_LOWER,
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
                                    G::LDT, true, MK_UPPER, rb, cp);
         acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_U, dd)), true, rb, cp);
       }
-    } else if (d <= 2 && r > t) {
+    } else if (d <= BandGeom::kChainD && r > t) {
       // L_m+d,m L_mm^-1: the new L tile (still in acc) goes to LDS
       acc_to_lds<R, T>(acc, lds, false, rb, cp);
       __syncthreads();
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_NONE, D, T, true, MK_UNIT_LOWER, rb,
                                  cp);
       acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_L, d)), true, rb, cp);
-    } else if (d <= 2) {
+    } else if (d <= BandGeom::kChainD) {
       // U_mm^-1 U_m,m+d: the new U tile (still in acc) goes to LDS
       acc_to_lds<R, T>(acc, lds, true, rb, cp);
       __syncthreads();

@@ -87,15 +87,18 @@ struct BandGeom {  // tile geometry of the band factor
   int NB;    // block rows: ceil(n / T)
   // Block row s stores its 2B+1 band tiles (s, s-B) .. (s, s+B), then the
   // kChain chain tiles of the solves' recurrences (rr_band.hip).
-  static constexpr int kChain = 8;  // chain_index() below
+  static constexpr int kChainD = 3;            // neighbour distances with chain tiles
+  static constexpr int kChain = 4 * kChainD;   // chain_index() below
   __host__ __device__ int row_tiles() const { return 2 * B + 1 + kChain; }
   __host__ __device__ int64_t tiles_per_omega() const { return (int64_t)NB * row_tiles(); }
 };
 
 // Chain tiles of block row s (formed by the factorisation, read by the
-// solves): one kind per sweep, for the neighbours at distance d = 1 and 2.
+// solves): one kind per sweep, for the neighbours at distance d = 1 .. kChainD.
 enum { CH_FWD_L = 0, CH_FWD_U = 1, CH_ADJ_U = 2, CH_ADJ_L = 3 };
-__host__ __device__ inline int chain_index(int kind, int d) { return 2 * kind + d - 1; }
+__host__ __device__ inline int chain_index(int kind, int d) {
+  return BandGeom::kChainD * kind + d - 1;
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, double hy,

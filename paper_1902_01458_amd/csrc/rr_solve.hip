@@ -176,10 +176,11 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
         aim[e] = (R)v.y;
       }
     }
-    // x_s = D_s^-1 (b_s - sum_{|t-s|>=3} T_st x_t) - G_s,2 x_s-+2 - G_s,1 x_s-+1
-    // (G: the chain tiles of rr_band.hip).  Far blocks were published long
-    // ago; D_s^-1 goes through LDS (every wave needs the whole column block);
-    // then the two neighbours, each one register MFMA product.
+    // x_s = D_s^-1 (b_s - sum_{|t-s|>C} T_st x_t) - sum_{d<=C} G_s,d x_s-+d with
+    // C = min(B, kChainD) (G: the chain tiles of rr_band.hip).  Far blocks
+    // were published long ago; D_s^-1 goes through LDS (every wave needs the
+    // whole column block); then the neighbours, nearest last, each one
+    // register MFMA product after its own wait.
     //   forward first: L_st (t < s), D = L^-1, G = CH_FWD_L
     //   forward second: U_st (t > s), D = U^-1, G = CH_FWD_U
     //   adjoint first: U_ts^H (t < s), D = (U^-1)^H, G = CH_ADJ_U^H
@@ -189,12 +190,13 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     const int mask = (ADJ ? second : !second) ? OPM_UNIT_LOWER : OPM_UPPER;
     const bool ut = ADJ != second;  // off-diagonal tiles of this sweep are U tiles (row-major)
     const int kind = ADJ ? (second ? CH_ADJ_L : CH_ADJ_U) : (second ? CH_FWD_U : CH_FWD_L);
+    const int C = min(B, (int)BandGeom::kChainD);
     Frag<R, T> fb;
     int f0, f1;
-    if (second) { f0 = s + 3; f1 = min(NB - 1, s + B); } else { f0 = max(0, s - B); f1 = s - 3; }
+    if (second) { f0 = s + C + 1; f1 = min(NB - 1, s + B); } else { f0 = max(0, s - B); f1 = s - C - 1; }
     if (f0 <= f1) {
-      // the older far blocks were published at least a step before the one
-      // three away: take them first, then wait for that one alone
+      // the older far blocks were published at least a step before the
+      // nearest far one: take them first, then wait for that one alone
       const int fn = second ? f0 : f1;
       const int g0 = second ? f0 + 1 : f0, g1 = second ? f1 : f1 - 1;
       if (g0 <= g1) {
@@ -222,27 +224,19 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
       load_b<R, T, NP>(fb, blk, cb);
       mma_frag<R, T, ADJ, false>(are, aim, a_diag, fb);
     }
-    // the neighbours at distance 2, then 1.  Chain tiles are factor data,
-    // final before the launch: their loads overlap the waits (a task is
-    // normally taken well before its neighbours are published).
-    const int nb1 = s + dir, nb2 = s + 2 * dir;
-    const bool has1 = nb1 >= 0 && nb1 < NB, has2 = B >= 2 && nb2 >= 0 && nb2 < NB;
-    // (in FP64 both chain fragments at once would not fit the register budget;
-    // the distance-1 one is then fetched after the distance-2 product)
-    constexpr bool kBoth = sizeof(R) == 4;
-    Frag<R, T> a1, a2;
-    if (has2) load_a<R, T, ADJ>(a2, chain(s, chain_index(kind, 2)), OPM_NONE, rb, ADJ);
-    if (kBoth && has1) load_a<R, T, ADJ>(a1, chain(s, chain_index(kind, 1)), OPM_NONE, rb, ADJ);
-    if (has2) {
-      wg_wait_range(fl, nb2, nb2, want, P.status);
-      load_b<R, T, NP>(fb, xw + (int64_t)nb2 * T * NP, cb);
-      mma_frag<R, T, ADJ, true>(are, aim, a2, fb);
-    }
-    if (!kBoth && has1) load_a<R, T, ADJ>(a1, chain(s, chain_index(kind, 1)), OPM_NONE, rb, ADJ);
-    if (has1) {
-      wg_wait_range(fl, nb1, nb1, want, P.status);
-      load_b<R, T, NP>(fb, xw + (int64_t)nb1 * T * NP, cb);
-      mma_frag<R, T, ADJ, true>(are, aim, a1, fb);
+    // the neighbours, farthest first.  Chain tiles are factor data, final
+    // before the launch, so each one's load is issued before the wait for its
+    // neighbour (a task is normally taken well before its neighbours are
+    // published).
+#pragma unroll 1
+    for (int d = C; d >= 1; d--) {
+      const int nb = s + d * dir;
+      if (nb < 0 || nb >= NB) continue;
+      Frag<R, T> ag;
+      load_a<R, T, ADJ>(ag, chain(s, chain_index(kind, d)), OPM_NONE, rb, ADJ);
+      wg_wait_range(fl, nb, nb, want, P.status);
+      load_b<R, T, NP>(fb, xw + (int64_t)nb * T * NP, cb);
+      mma_frag<R, T, ADJ, true>(are, aim, ag, fb);
     }
     cplx<R>* xs = xw + (int64_t)s * T * NP;
 #pragma unroll
