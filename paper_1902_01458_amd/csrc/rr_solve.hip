@@ -86,12 +86,13 @@ struct Solve2Params {
   const double2* Bm;
   int64_t bstride;   // complex elements between the shifts' right-hand sides
   double2* X;        // (n_omega, k, n) result
-  void* xs;          // workspace: n_omega * NB * T * NP complex R, row-major blocks
-  int* flags;        // n_omega * NB: 1 = first sweep done, 2 = final
+  void* xs;          // workspace: n_omega * ngroups * NB * T * NP complex R, row-major blocks
+  int* flags;        // n_omega * ngroups * NB: 1 = first sweep done, 2 = final
   uint32_t* ticket;
   uint32_t* status;
-  int64_t total;     // n_omega * 2 * NB
+  int64_t total;     // n_omega * ngroups * 2 * NB
   const uint32_t* skip;  // optional: non-zero at run time = nothing to do
+  int ngroups;       // column groups of NP right-hand sides, solved independently
 };
 
 // Thread 0 polls flags [t0, t1] of one shift until each reaches `want`, then
@@ -129,31 +130,46 @@ __device__ __forceinline__ void wg_publish_one(int* flag, int value) {
   __syncthreads();
 }
 
+// Chain tiles a solve task stages in LDS: three in FP32, two in FP64 (the
+// 64-wide FP64 layout, 32 KiB + 2 x 64 KiB, fills the 160 KiB of a CU).
+template <typename R>
+constexpr int kChainLds() {
+  return sizeof(R) == 4 ? 2 : 1;
+}
+
 template <typename R, int T, int NP, bool ADJ>
-__global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Params P) {
+__global__ __launch_bounds__(64 * (T / 16) * (NP / 16), 2) void k_solve2(Solve2Params P) {
   if (P.skip && __hip_atomic_load(P.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   constexpr int NCB = NP / 16;
+  constexpr int NT = 64 * (T / 16) * (NP / 16);
   extern __shared__ __align__(16) char solve_smem[];
   cplx<R>* blk = reinterpret_cast<cplx<R>*>(solve_smem);  // pre-diagonal block, row-major
-  __shared__ uint32_t s_ticket;
+  cplx<R>* gl = blk + T * NP;  // copies of the chain tiles d = 1 .. kChainLds (T*T each)
+  // the ticket broadcast word shares the staging block (free when a ticket is
+  // taken), so that the FP64 layout fits the 160 KiB of LDS exactly
+  uint32_t* s_ticket = reinterpret_cast<uint32_t*>(solve_smem);
   typedef typename Mf<R>::v4 v4;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rb = wave / NCB, cb = wave % NCB;
   const int B = P.g.B, NB = P.g.NB, RT = P.g.row_tiles();
   for (;;) {
-    const int64_t ticket = wg_ticket(P.ticket, &s_ticket);
+    const int64_t ticket = wg_ticket(P.ticket, s_ticket);
     if (ticket >= P.total) break;
-    const int w = (int)(ticket % P.n_omega);
-    const int64_t task = ticket / P.n_omega;
+    // (shift, column group) pairs are independent chains of the same factor
+    const int nv = P.n_omega * P.ngroups;
+    const int wv = (int)(ticket % nv);
+    const int w = wv / P.ngroups, grp = wv % P.ngroups;
+    const int64_t task = ticket / nv;
     const bool second = task >= NB;
     const int s = second ? (int)(2 * NB - 1 - task) : (int)task;
-    int* fl = P.flags + (int64_t)w * NB;
+    int* fl = P.flags + (int64_t)wv * NB;
     const cplx<R>* tw =
         reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)w * NB * RT * (T * T);
     auto tile = [&](int r, int t) { return tw + ((int64_t)r * RT + (t - r + B)) * (T * T); };
     auto chain = [&](int r, int c) { return tw + ((int64_t)r * RT + 2 * B + 1 + c) * (T * T); };
-    cplx<R>* xw = reinterpret_cast<cplx<R>*>(P.xs) + (int64_t)w * NB * T * NP;
+    cplx<R>* xw = reinterpret_cast<cplx<R>*>(P.xs) + (int64_t)wv * NB * T * NP;
     const int j = 16 * cb + (l & 15);  // this lane's column in the block
+    const int jg = grp * NP + j;       // and among the right-hand sides
     v4 are, aim;
     // right-hand side: b_s (first sweep) or the first sweep's y_s (second)
     if (second) {
@@ -171,7 +187,7 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
       for (int e = 0; e < 4; e++) {
         int64_t r = (int64_t)s * T + 16 * rb + Mf<R>::row(l, e);
         double2 v = make_double2(0.0, 0.0);
-        if (j < P.k && r < P.n) v = Bw[(int64_t)j * P.n + r];
+        if (jg < P.k && r < P.n) v = Bw[(int64_t)jg * P.n + r];
         are[e] = (R)v.x;
         aim[e] = (R)v.y;
       }
@@ -191,6 +207,17 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     const bool ut = ADJ != second;  // off-diagonal tiles of this sweep are U tiles (row-major)
     const int kind = ADJ ? (second ? CH_ADJ_L : CH_ADJ_U) : (second ? CH_FWD_U : CH_FWD_L);
     const int C = min(B, (int)BandGeom::kChainD);
+    // the nearest chain tiles go to LDS now, off the dependency chain, so that
+    // the products near the chain read their operand at LDS latency
+    const int CL = min(C, kChainLds<R>());
+    for (int d = 1; d <= CL; d++) {
+      if (s + d * dir < 0 || s + d * dir >= NB) break;
+      const cplx<R>* g = chain(s, chain_index(kind, d));
+      cplx<R>* gd = gl + (d - 1) * T * T;
+#pragma unroll 2
+      for (int idx = threadIdx.x; idx < T * T; idx += NT) gd[idx] = g[idx];
+      __builtin_amdgcn_sched_barrier(0);
+    }
     Frag<R, T> fb;
     int f0, f1;
     if (second) { f0 = s + C + 1; f1 = min(NB - 1, s + B); } else { f0 = max(0, s - B); f1 = s - C - 1; }
@@ -229,13 +256,23 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
     // neighbour (a task is normally taken well before its neighbours are
     // published).
 #pragma unroll 1
-    for (int d = C; d >= 1; d--) {
+    for (int d = C; d > CL; d--) {  // chain tiles not staged in LDS
       const int nb = s + d * dir;
       if (nb < 0 || nb >= NB) continue;
       Frag<R, T> ag;
       load_a<R, T, ADJ>(ag, chain(s, chain_index(kind, d)), OPM_NONE, rb, ADJ);
       wg_wait_range(fl, nb, nb, want, P.status);
       load_b<R, T, NP>(fb, xw + (int64_t)nb * T * NP, cb);
+      mma_frag<R, T, ADJ, true>(are, aim, ag, fb);
+    }
+#pragma unroll 1
+    for (int d = CL; d >= 1; d--) {  // staged in LDS; d = 1 is the chain itself
+      const int nb = s + d * dir;
+      if (nb < 0 || nb >= NB) continue;
+      wg_wait_range(fl, nb, nb, want, P.status);
+      load_b<R, T, NP>(fb, xw + (int64_t)nb * T * NP, cb);
+      Frag<R, T> ag;
+      load_a<R, T, ADJ>(ag, gl + (d - 1) * T * T, OPM_NONE, rb, ADJ);
       mma_frag<R, T, ADJ, true>(are, aim, ag, fb);
     }
     cplx<R>* xs = xw + (int64_t)s * T * NP;
@@ -248,16 +285,24 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16)) void k_solve2(Solve2Para
 #pragma unroll
       for (int e = 0; e < 4; e++) {
         int64_t r = (int64_t)s * T + 16 * rb + Mf<R>::row(l, e);
-        if (j < P.k && r < P.n) Xw[(int64_t)j * P.n + r] = make_double2((double)are[e], (double)aim[e]);
+        if (jg < P.k && r < P.n)
+          Xw[(int64_t)jg * P.n + r] = make_double2((double)are[e], (double)aim[e]);
       }
     }
     wg_publish_one(fl + s, want);
   }
 }
 
+// LDS of a solve workgroup: the T x NP staging block and kChainLds() T x T
+// chain tiles.
+template <typename R, int T, int NP>
+constexpr size_t solve_lds() {
+  return sizeof(cplx<R>) * ((size_t)T * NP + (size_t)kChainLds<R>() * T * T);
+}
+
 template <typename R, int T, int NP, bool ADJ>
 static hipError_t launch_a(const Solve2Params& P, int grid, hipStream_t s) {
-  size_t lds = sizeof(cplx<R>) * (size_t)T * NP;
+  const size_t lds = solve_lds<R, T, NP>();
   hipLaunchKernelGGL((k_solve2<R, T, NP, ADJ>), dim3(grid), dim3(64 * (T / 16) * (NP / 16)), lds,
                      s, P);
   return hipGetLastError();
@@ -269,12 +314,10 @@ static hipError_t prepare_t() {
   auto set = [&](const void* fn, int np) {
     if (e == hipSuccess)
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(cplx<R>) * T * np));
+                              (int)(np == 16 ? solve_lds<R, T, 16>() : solve_lds<R, T, 32>()));
   };
   set((const void*)k_solve2<R, T, 16, false>, 16);
   set((const void*)k_solve2<R, T, 16, true>, 16);
-  set((const void*)k_solve2<R, T, 32, false>, 32);
-  set((const void*)k_solve2<R, T, 32, true>, 32);
   return e;
 }
 
@@ -292,10 +335,7 @@ static hipError_t launch_t(const Solve2Params& P, int grid, hipStream_t s) {
 
 template <typename R, int T>
 static hipError_t launch_np(const Solve2Params& P, int NP, int grid, hipStream_t s) {
-  switch (NP) {
-    case 16: return launch_t<R, T, 16>(P, grid, s);
-    case 32: return launch_t<R, T, 32>(P, grid, s);
-  }
+  if (NP == 16) return launch_t<R, T, 16>(P, grid, s);
   return hipErrorInvalidValue;
 }
 
@@ -305,11 +345,15 @@ hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
                         double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
                         int grid, hipStream_t s, const uint32_t* skip) {
-  int NP = solve_np(k);
-  if (NP > 32) return hipErrorInvalidValue;  // k <= 32 (rr_factor's k_max bound)
+  // The right-hand sides are split into groups of 16 columns, each an
+  // independent chain: half the MFMA work per block step on the chain for
+  // k in (16, 32], and twice the chains in flight.
+  const int NP = 16, ngroups = solve_np(k) / 16;
+  if (ngroups > 2) return hipErrorInvalidValue;  // k <= 32 (rr_factor's k_max bound)
   Solve2Params P{g, n, n_omega, k, adjoint, tiles, (const double2*)Bm, bstride, (double2*)X,
-                 xs, flags, ticket, status, (int64_t)n_omega * 2 * g.NB, skip};
-  hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.NB, s);
+                 xs, flags, ticket, status, (int64_t)n_omega * ngroups * 2 * g.NB, skip,
+                 ngroups};
+  hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * ngroups * g.NB, s);
   if (e == hipSuccess) e = launch_fill_u32(ticket, 0u, 1, s);
   if (e != hipSuccess) return e;
   if (grid > P.total) grid = (int)P.total;
