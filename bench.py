@@ -235,7 +235,7 @@ def main():
     }
     if fp64 is not None:
         a64 = flops / (fp64["factor_ms"] * 1e-3) / 1e12
-        sk = f"k_solve2<double,{fp64['tune']['tile']},32,true>"
+        sk = f"k_solve2<double,{fp64['tune']['tile']},16,true>"
         bw = solve_bytes / (fp64["calls_ms"]["adjoint"] * 1e-3) / 1e9
         line["fp64"] = {"value": n_om / (fp64["ms_per_step"] * 1e-3),
                         "ms_per_step": fp64["ms_per_step"], "calls_ms": fp64["calls_ms"],
