@@ -74,7 +74,7 @@ rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
 void free_all(rr_factors* f) {
   void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->flags, f->ctrl, f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
-                f->small.Rinv, f->small.W, f->small.Ut, f->grad_partial};
+                f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->grad_partial};
   for (void* p : ps) {
     if (!p) continue;
     if (f->dealloc) f->dealloc(p, f->alloc_ctx);
@@ -124,7 +124,7 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
                         (int64_t)k * f->n, res, f->xs, f->flags, ticket_word(f), st_word(f),
                         f->solve_grid, s, conv_word(f)));
     RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
-    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, f->small, st_word(f),
+    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, it, f->small, st_word(f),
                                 fail_word(f), s, conv_word(f)));
     hipLaunchKernelGGL(k_refine_step, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
                        f->ctrl + 4 + it, conv_word(f));
@@ -138,12 +138,12 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
 // Device allocations of a handle, in one place for rr_factor and rr_factor_bytes.
 struct Plan {
   BandGeom geom;
-  size_t coef, phi, U, omega, tiles, xs, flags, ctrl, theta, vec, work3, partial, kk2, grad;
+  size_t coef, phi, U, omega, tiles, xs, flags, ctrl, theta, vec, work3, partial, kk2, rho, grad;
   int nchunk, grad_nchunk;
   size_t nflags;
   size_t total() const {
     return coef + phi + U + omega + tiles + xs + flags + ctrl + theta + 2 * vec + work3 + partial +
-           5 * kk2 + grad;
+           5 * kk2 + rho + grad;
   }
 };
 
@@ -172,6 +172,7 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   const size_t kk = (size_t)std::max(k_max * k_max, 64);
   pl.partial = (size_t)n_omega * pl.nchunk * kk * 2 * sizeof(double);
   pl.kk2 = (size_t)n_omega * kk * 2 * sizeof(double);
+  pl.rho = prec == RR_MIXED ? (size_t)n_omega * 64 * sizeof(double) : 0;
   pl.grad_nchunk = (int)((nn + 255) / 256);
   pl.grad = (size_t)n_omega * pl.grad_nchunk * 2 * sizeof(double);
   return pl;
@@ -302,6 +303,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   ALLOC(f->small.Rinv, pl.kk2);
   ALLOC(f->small.W, pl.kk2);
   ALLOC(f->small.Ut, pl.kk2);
+  if (prec == RR_MIXED) ALLOC(f->small.rho, pl.rho);
   f->small.nchunk = pl.nchunk;
   f->small.kmax = k_max;
   f->grad_nchunk = pl.grad_nchunk;

@@ -9,9 +9,12 @@
 //   A_rt -= sum_s L_rs U_st             (updates, complex GEMMs on MFMA)
 //   A_mm  = L_mm U_mm                    (T x T LU in LDS)
 //   L_rm  = A_rm U_mm^-1,  U_mt = L_mm^-1 A_mt
-// The diagonal tile is stored as [U_mm^-1 (upper, diagonal included) |
-// L_mm^-1 (strictly lower, unit diagonal implied)], so the solves and the
-// off-diagonal finalisations are GEMMs too.
+// The diagonal step publishes the LU with its 16 x 16 diagonal blocks
+// inverted first; the off-diagonal finalisations are triangular solves with
+// it (wave-local, on MFMA).  The full inverses follow off the dependency
+// chain, and the diagonal tile is stored as [U_mm^-1 (upper, diagonal
+// included) | L_mm^-1 (strictly lower, unit diagonal implied)] for the
+// solves, where applying D^-1 is a GEMM.
 //
 // Storage: L tiles (r > t) and diagonal tiles are column-major, U tiles
 // (r < t) row-major, so that in the update L_rs U_st both MFMA operands are
@@ -23,11 +26,14 @@
 // m = min(r, t) there are two tasks:
 //   E(r, t)  the early updates s <= m-2 (inputs final long before), written
 //            back as a partial tile (flag 1); issued one step ahead
-//   F(r, t)  the last update s = m-1 and the finalisation (flag 2)
+//   F(r, t)  the last update s = m-1 (before waiting on the diagonal tile m)
+//            and the finalisation (flag 2; the diagonal tile 2, then 3 once
+//            its full inverses are stored)
 // so the chain from one diagonal block to the next carries one update GEMM,
-// one finalisation GEMM and one T x T LU.  The tile of M itself is generated
+// one triangular solve and one T x T LU.  The tile of M itself is generated
 // from the stencil in registers: the band is never read before it is final.
-// Every tile store is device-coherent (st_coherent): a tile is written twice
+// Every tile store is device-coherent (st_coherent) and goes through LDS so
+// that each store instruction writes whole lines: a tile is written twice
 // per launch, from different XCDs in general, and read from others.
 //
 // Chain tiles.  In each sweep of a solve, block s depends on the blocks t
@@ -42,8 +48,8 @@
 //   CH_ADJ_U,d = U_s-d,s U_ss^-1   (row-major)      adjoint, U^H sweep (used as ^H)
 //   CH_ADJ_L,d = L_s+d,s L_ss^-1   (row-major)      adjoint, L^H sweep (used as ^H)
 // F(s, s) forms CH_FWD_L and CH_ADJ_U after publishing D_s; F(s+d, s) and
-// F(s, s+d) form CH_ADJ_L,d and CH_FWD_U,d after publishing their tile.
-// Nothing in the launch waits on chain tiles.
+// F(s, s+d) form CH_ADJ_L,d and CH_FWD_U,d after publishing their tile (and
+// waiting for D_s).  Nothing in the launch waits on chain tiles.
 #include "rr_mfma.h"
 
 namespace rr {
@@ -161,119 +167,136 @@ __device__ __forceinline__ void blk_store(const typename Mf<R>::v4& re,
     S[(c0 + (l & 15)) * ld + r0 + Mf<R>::row(l, e)] = cplx<R>{re[e], im[e]};
 }
 
-// No-pivot LU of the T x T tile S (LDS, column-major, leading dimension LD)
-// and in-place inversion of both triangles,
-//   S <- [U^-1 on and above the diagonal | L^-1 strictly below],
-// blocked so that the sequential part is short and wave-local:
-//  LU, per 16-column panel: one wave factors the panel (lane = row, the
-//    pivot row broadcast lane to lane, no barriers), then U12 = L11^-1 A12 by
-//    forward substitution (thread = column), then A22 -= L21 U12 on MFMA;
-//  inverses: the 16 x 16 diagonal blocks by substitution (one wave each),
-//    then doubling: [[A, 0], [C, D]]^-1 has lower-left -D^-1 C A^-1, and
-//    [[A, B], [0, D]]^-1 upper-right -A^-1 B D^-1, two MFMA products per level
-//    (tmp: T*T/2 complex of LDS for the intermediate products).
+// Inverse of the 16 x 16 diagonal block at (b0, b0) of an LU held in LDS
+// (column-major, leading dimension LD), in place: unit-lower L (its strictly
+// lower part is rewritten) or upper U (the upper part with the diagonal).
+// Lane c computes column c of the inverse by substitution in registers,
+// reading the triangle's entries as wave-uniform (broadcast) LDS loads; lanes
+// 16 .. 63 compute copies and store nothing.  The other triangle of the block is
+// neither read nor written, so the L and U inversions of one block may run
+// in two waves at once.
+// z unchanged, but the compiler must take it as computed from v as well:
+// loads addressed with it wait for v, which keeps them from being hoisted
+// ahead of the values they are used with (register pressure).
+__device__ __forceinline__ int zero_after(int z, float v) {
+  asm volatile("" : "=v"(z) : "0"(z), "v"(v));
+  return z;
+}
+__device__ __forceinline__ int zero_after(int z, double v) {
+  asm volatile("" : "=v"(z) : "0"(z), "v"(v));
+  return z;
+}
+
+template <typename R>
+__device__ __forceinline__ void inv_diag16(cplx<R>* S, int LD, int b0, bool isL) {
+  const int lane = threadIdx.x & 63, c = lane & 15;
+  cplx<R> x[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) x[i] = cplx<R>{i == c ? (R)1 : (R)0, (R)0};
+  // column-oriented substitution: once x_j is final it is eliminated from the
+  // rows still open; column j of the triangle is loaded only after column
+  // j - 1 is done (z), so one column is live at a time
+  int z = 0;
+  if (isL) {
+#pragma unroll
+    for (int j = 0; j < 15; j++) {
+      const cplx<R>* col = S + (b0 + j) * LD + b0 + z;
+#pragma unroll
+      for (int i = j + 1; i < 16; i++) {
+        csub_mul(x[i], col[i], x[j]);
+        z = zero_after(z, x[i].re);
+      }
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 1; i < 16; i++)
+        if (i > c) S[(b0 + c) * LD + b0 + i] = x[i];
+    }
+  } else {
+#pragma unroll
+    for (int j = 15; j >= 0; j--) {
+      const cplx<R>* col = S + (b0 + j) * LD + b0 + z;
+      x[j] = cmul(x[j], cinv(col[j]));
+#pragma unroll
+      for (int i = 0; i < j; i++) {
+        csub_mul(x[i], col[i], x[j]);
+        z = zero_after(z, x[i].re);
+      }
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; i++)
+        if (i <= c) S[(b0 + c) * LD + b0 + i] = x[i];
+    }
+  }
+}
+
+// No-pivot LU of the T x T tile S (LDS, column-major, leading dimension LD),
+// then in-place inversion of its 16 x 16 diagonal blocks:
+//   S <- L (strictly lower, unit diagonal implied) and U (upper, diagonal
+//        included), each diagonal block L_jj, U_jj replaced by its inverse
+// (the block-inverse LU: enough for the triangular solves of the
+// off-diagonal finalisations).  Blocked so that the sequential part is short
+// and wave-local: per 16-column panel one wave factors the panel in registers
+// (lane = row, the pivot row broadcast lane to lane), then U12 = L11^-1 A12 by
+// forward substitution (thread = column, in registers), then A22 -= L21 U12
+// on MFMA; the diagonal blocks are inverted by substitution (inv_diag16).
 // A zero or non-finite pivot latches ST_SINGULAR and is replaced by 1.
 template <typename R, int T, int NW>
-__device__ void lu_inv_tile(cplx<R>* S, int LD, cplx<R>* tmp, uint32_t* status) {
+__device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
   typedef typename Mf<R>::v4 v4;
   constexpr int P = 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const cplx<R> one{(R)1, (R)0}, zero{(R)0, (R)0};
   auto at = [&](int i, int c) -> cplx<R>& { return S[c * LD + i]; };
-  // panel rows and U12 columns in registers (in the FP64 64-wide kernel this
-  // pushes a few long-lived values of the task loop to scratch, measured
-  // cheaper than the LDS panel: 433 against 506 ms for 16 shifts at n = 262144)
-  constexpr bool kRegPanel = true;
-  constexpr bool kRegTrsm = true;
 #pragma unroll 1
   for (int c0 = 0; c0 < T; c0 += P) {
-    if (kRegPanel) {
-      // panel in registers: lane = row c0 + lane, the pivot row broadcast
-      // lane to lane (no LDS round trip per step)
-      if (wave == 0) {
-        const int r = c0 + lane;
-        const bool act = r < T;
-        cplx<R> a[P];
+    // panel: lane = row c0 + lane
+    if (wave == 0) {
+      const int r = c0 + lane;
+      const bool act = r < T;
+      cplx<R> a[P];
 #pragma unroll
-        for (int c = 0; c < P; c++) a[c] = act ? at(r, c0 + c) : zero;
+      for (int c = 0; c < P; c++) a[c] = act ? at(r, c0 + c) : zero;
 #pragma unroll
-        for (int j = 0; j < P; j++) {
-          cplx<R> p = bcast(a[j], j);
-          const R mag = p.re * p.re + p.im * p.im;
-          if (!(mag > (R)0) || !isfinite(mag)) {
-            if (lane == 0) latch(status, ST_SINGULAR);
-            if (lane == j) a[j] = one;
-            p = one;
-          }
-          const cplx<R> l = cmul(a[j], cinv(p));
-          const bool below = act && lane > j;
-          if (below) a[j] = l;
-#pragma unroll
-          for (int c = j + 1; c < P; c++) {
-            const cplx<R> u = bcast(a[c], j);
-            if (below) csub_mul(a[c], l, u);
-          }
-          __builtin_amdgcn_sched_barrier(0);
+      for (int j = 0; j < P; j++) {
+        cplx<R> p = bcast(a[j], j);
+        const R mag = p.re * p.re + p.im * p.im;
+        if (!(mag > (R)0) || !isfinite(mag)) {
+          if (lane == 0) latch(status, ST_SINGULAR);
+          if (lane == j) a[j] = one;
+          p = one;
         }
+        const cplx<R> l = cmul(a[j], cinv(p));
+        const bool below = act && lane > j;
+        if (below) a[j] = l;
 #pragma unroll
-        for (int c = 0; c < P; c++)
-          if (act) at(r, c0 + c) = a[c];
-      }
-    } else {
-      // panel: one wave, lane = row c0 + lane.  Step j writes only rows below
-      // the pivot, each lane its own row, and reads the pivot row, so the
-      // steps need no barrier (one wave: LDS keeps issue order).
-      if (wave == 0) {
-        const int i = c0 + lane;
-#pragma unroll 1
-        for (int j = c0; j < c0 + P; j++) {
-          cplx<R> p = at(j, j);
-          const R mag = p.re * p.re + p.im * p.im;
-          if (!(mag > (R)0) || !isfinite(mag)) {
-            if (lane == 0) {
-              latch(status, ST_SINGULAR);
-              at(j, j) = one;
-            }
-            p = one;
-          }
-          if (i > j && i < T) {
-            const cplx<R> l = cmul(at(i, j), cinv(p));
-            at(i, j) = l;
-#pragma unroll 4
-            for (int c = j + 1; c < c0 + P; c++) csub_mul(at(i, c), l, at(j, c));
-          }
+        for (int c = j + 1; c < P; c++) {
+          const cplx<R> u = bcast(a[c], j);
+          if (below) csub_mul(a[c], l, u);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int c = 0; c < P; c++)
+        if (act) at(r, c0 + c) = a[c];
     }
     __syncthreads();
     if (c0 + P >= T) break;
-    if (kRegTrsm) {
-      // U12 = L11^-1 A12: thread t owns column c0 + P + t, held in registers
-      if (threadIdx.x < T - c0 - P) {
-        const int c = c0 + P + threadIdx.x;
-        cplx<R> x[P];
+    // U12 = L11^-1 A12: thread t owns column c0 + P + t
+    if (threadIdx.x < T - c0 - P) {
+      const int c = c0 + P + threadIdx.x;
+      cplx<R> x[P];
 #pragma unroll
-        for (int i = 0; i < P; i++) x[i] = at(c0 + i, c);
+      for (int i = 0; i < P; i++) x[i] = at(c0 + i, c);
 #pragma unroll
-        for (int j = 0; j < P - 1; j++) {
+      for (int j = 0; j < P - 1; j++) {
 #pragma unroll
-          for (int i = j + 1; i < P; i++) csub_mul(x[i], at(c0 + i, c0 + j), x[j]);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-        for (int i = 0; i < P; i++) at(c0 + i, c) = x[i];
+        for (int i = j + 1; i < P; i++) csub_mul(x[i], at(c0 + i, c0 + j), x[j]);
+        __builtin_amdgcn_sched_barrier(0);
       }
-    } else {
-      // U12 = L11^-1 A12: thread t owns column c0 + P + t (writes only that column)
-      if (threadIdx.x < T - c0 - P) {
-        const int c = c0 + P + threadIdx.x;
-#pragma unroll 1
-        for (int j = c0; j < c0 + P - 1; j++) {
-          const cplx<R> xj = at(j, c);
-#pragma unroll 4
-          for (int i = j + 1; i < c0 + P; i++) csub_mul(at(i, c), at(i, j), xj);
-        }
-      }
+#pragma unroll
+      for (int i = 0; i < P; i++) at(c0 + i, c) = x[i];
     }
     __syncthreads();
     // A22 -= L21 U12 in 16 x 16 blocks
@@ -288,56 +311,22 @@ __device__ void lu_inv_tile(cplx<R>* S, int LD, cplx<R>* tmp, uint32_t* status) 
     __syncthreads();
   }
   // inverses of the 16 x 16 diagonal blocks, in place, one wave per block
-  // (tasks 0 .. T/16-1: L blocks, the rest U blocks).  Each step reads all
-  // its operands before any lane stores (one wave: LDS keeps issue order).
+  // (tasks 0 .. T/16-1: L blocks, the rest U blocks)
   constexpr int NDB = T / 16;
-  for (int tsk = wave; tsk < 2 * NDB; tsk += NW) {
-    const bool isL = tsk < NDB;
-    const int b0 = 16 * (isL ? tsk : tsk - NDB);
-    auto bt = [&](int i, int c) -> cplx<R>& { return S[(b0 + c) * LD + b0 + i]; };
-#pragma unroll 1
-    for (int st = 0; st < 16; st++) {
-      cplx<R> nv[4];
-      bool wr[4];
-      if (isL) {
-        // step j = st: X[i][c] -= L[i][j] X[j][c] for i > j, c <= j (X[j][j] = 1)
-        const int jx = st;
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          const int idx = lane + 64 * e, i = idx % 16, c = idx / 16;
-          wr[e] = i > jx && c <= jx;
-          const cplx<R> m = bt(i, jx);
-          const cplx<R> xj = (c == jx) ? one : bt(jx, c);
-          nv[e] = (c == jx) ? zero : bt(i, c);
-          csub_mul(nv[e], m, xj);
-        }
-      } else {
-        // step jj = 15 - st: row jj <- acc / U[jj][jj]; rows i < jj:
-        // acc[i][c] -= U[i][jj] X[jj][c] for c >= jj
-        const int jj = 15 - st;
-        const cplx<R> iu = cinv(bt(jj, jj));
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          const int idx = lane + 64 * e, i = idx % 16, c = idx / 16;
-          const cplx<R> xj = (c == jj) ? iu : cmul(bt(jj, c), iu);
-          wr[e] = i <= jj && c >= jj;
-          if (i == jj) {
-            nv[e] = xj;
-          } else {
-            nv[e] = (c == jj) ? zero : bt(i, c);
-            csub_mul(nv[e], bt(i, jj), xj);
-          }
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int idx = lane + 64 * e;
-        if (wr[e]) bt(idx % 16, idx / 16) = nv[e];
-      }
-    }
-  }
+  for (int tsk = wave; tsk < 2 * NDB; tsk += NW)
+    inv_diag16<R>(S, LD, 16 * (tsk < NDB ? tsk : tsk - NDB), tsk < NDB);
   __syncthreads();
-  // doubling: blocks of 2h along the diagonal; kind 0 = L, 1 = U
+}
+
+// Block-inverse LU (lu_blockinv) -> [U^-1 on and above the diagonal | L^-1
+// strictly below], in place, by doubling: [[A, 0], [C, D]]^-1 has lower-left
+// -D^-1 C A^-1 and [[A, B], [0, D]]^-1 upper-right -A^-1 B D^-1, two MFMA
+// products per level (tmp: T*T/2 complex of LDS for the intermediate products).
+template <typename R, int T, int NW>
+__device__ void inv_doubling(cplx<R>* S, int LD, cplx<R>* tmp) {
+  typedef typename Mf<R>::v4 v4;
+  const int wave = threadIdx.x >> 6;
+  // blocks of 2h along the diagonal; kind 0 = L, 1 = U
 #pragma unroll 1
   for (int h = 16; h < T; h *= 2) {
     const int nblk = T / (2 * h), nsub = (h / 16) * (h / 16);
@@ -377,6 +366,54 @@ __device__ void lu_inv_tile(cplx<R>* S, int LD, cplx<R>* tmp, uint32_t* status) 
       }
     }
     __syncthreads();
+  }
+}
+
+// Triangular solves with a block-inverse LU Db (LDS, column-major, leading
+// dimension LDD), in place on the T x T tile S (LDS, column-major, leading
+// dimension LD).  Both are wave-local (no barriers): the waves below T/16
+// each own one 16-row (right solve) or 16-column (left solve) strip and walk
+// its blocks in dependency order; the other waves return at once.
+//   right, upper:      S <- S U^-1:  X_j = (A_j - sum_{i<j} X_i U_ij) U_jj^-1
+//   left, unit lower:  S <- L^-1 S:  X_i = L_ii^-1 (A_i - sum_{k<i} L_ik X_k)
+template <typename R, int T>
+__device__ __forceinline__ void trsm_right_upper(cplx<R>* S, int LD, const cplx<R>* Db, int LDD) {
+  typedef typename Mf<R>::v4 v4;
+  const int wave = threadIdx.x >> 6;
+  if (wave >= T / 16) return;
+  const int r0 = 16 * wave;
+#pragma unroll 1
+  for (int j = 0; j < T / 16; j++) {
+    v4 re, im;
+    blk_load<R>(re, im, S, LD, r0, 16 * j);
+    if (j > 0)
+      lds_blk_gemm<R, true>(re, im, S, LD, r0, 0, MK_NONE, Db, LDD, 0, 16 * j, MK_NONE, 16 * j);
+    blk_store<R>(re, im, S, LD, r0, 16 * j);
+#pragma unroll
+    for (int e = 0; e < 4; e++) { re[e] = 0; im[e] = 0; }
+    lds_blk_gemm<R, false>(re, im, S, LD, r0, 16 * j, MK_NONE, Db, LDD, 16 * j, 16 * j, MK_UPPER,
+                           16);
+    blk_store<R>(re, im, S, LD, r0, 16 * j);
+  }
+}
+template <typename R, int T>
+__device__ __forceinline__ void trsm_left_lower(cplx<R>* S, int LD, const cplx<R>* Db, int LDD) {
+  typedef typename Mf<R>::v4 v4;
+  const int wave = threadIdx.x >> 6;
+  if (wave >= T / 16) return;
+  const int c0 = 16 * wave;
+#pragma unroll 1
+  for (int i = 0; i < T / 16; i++) {
+    v4 re, im;
+    blk_load<R>(re, im, S, LD, 16 * i, c0);
+    if (i > 0)
+      lds_blk_gemm<R, true>(re, im, Db, LDD, 16 * i, 0, MK_NONE, S, LD, 0, c0, MK_NONE, 16 * i);
+    blk_store<R>(re, im, S, LD, 16 * i, c0);
+#pragma unroll
+    for (int e = 0; e < 4; e++) { re[e] = 0; im[e] = 0; }
+    lds_blk_gemm<R, false>(re, im, Db, LDD, 16 * i, 16 * i, MK_UNIT_LOWER, S, LD, 16 * i, c0,
+                           MK_NONE, 16);
+    blk_store<R>(re, im, S, LD, 16 * i, c0);
   }
 }
 
@@ -441,9 +478,13 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
 //   slot 0: F(m, m); 1: F(m+1, m); 2: F(m, m+1)
 //   slots 3 .. 2B-1: E of the tiles finalised at step m+1 (distance <= B-2)
 //   slots 2B .. 4B-3: F at distance 2 .. B
+// (Issuing F(m+1, m+1) early, right after its inputs, measured slower: its
+// workgroup then waits a whole step and the other tasks start later.)
 struct Task {
   int kind, r, t;
 };
+
+__host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B - 2 : 3; }
 
 __device__ __forceinline__ Task decode(int slot, int m, int B) {
   if (slot == 0) return {0, m, m};
@@ -482,6 +523,55 @@ __device__ __forceinline__ cplx<R>* chain_ptr(const FactorParams& P, int w, int 
 __device__ __forceinline__ int* flag_ptr(const FactorParams& P, int w, int r, int t) {
   const int W = 2 * P.g.B + 1;
   return P.flags + ((int64_t)w * P.g.NB + r) * W + (t - r + P.g.B);
+}
+
+// acc -= sum_{s = s0 .. s1} L_rs U_st for the tile (r, t), operands straight
+// from global memory (L tiles column-major, U tiles row-major).  The KQ-step
+// chunks of all the products form one sequence, loaded one chunk ahead of
+// the MFMAs (two register buffers), so that only the first load's latency is
+// exposed; the chunk count per product is even, so the loop needs no tail.
+template <typename R, int T, int KQ>
+struct UpdChunk {
+  cplx<R> a[KQ], b0[KQ], b1[KQ];
+};
+
+template <typename R, int T, int KQ>
+__device__ __forceinline__ void update_gemms(Acc2<R>& acc, const FactorParams& P, int w, int r,
+                                             int t, int s0, int s1, int rb, int cp) {
+  constexpr int NKC = T / 4 / KQ;  // chunks per product
+  static_assert(NKC % 2 == 0, "even chunk count");
+  const int N = (s1 - s0 + 1) * NKC;
+  if (N <= 0) return;
+  const int l = threadIdx.x & 63;
+  const int i = 16 * rb + (l & 15), j0 = 32 * cp + (l & 15);
+  auto load = [&](UpdChunk<R, T, KQ>& c, int idx) {
+    const int s = s0 + idx / NKC, kq = (idx % NKC) * KQ;
+    const cplx<R>* A = tile_ptr<R, T>(P, w, r, s);
+    const cplx<R>* Bm = tile_ptr<R, T>(P, w, s, t);
+#pragma unroll
+    for (int q = 0; q < KQ; q++) {
+      const int k = 4 * (kq + q) + (l >> 4);
+      c.a[q] = A[k * T + i];
+      c.b0[q] = Bm[k * T + j0];
+      c.b1[q] = Bm[k * T + j0 + 16];
+    }
+  };
+  auto mma = [&](const UpdChunk<R, T, KQ>& c) {
+#pragma unroll
+    for (int q = 0; q < KQ; q++) {
+      cmfma<R, false, true>(acc.re[0], acc.im[0], c.a[q], c.b0[q]);
+      cmfma<R, false, true>(acc.re[1], acc.im[1], c.a[q], c.b1[q]);
+    }
+  };
+  UpdChunk<R, T, KQ> c0, c1;
+  load(c0, 0);
+#pragma unroll 1
+  for (int idx = 0; idx < N; idx += 2) {
+    load(c1, idx + 1);
+    mma(c0);
+    load(c0, min(idx + 2, N - 1));  // the last one reloads a chunk (unused)
+    mma(c1);
+  }
 }
 
 // Thread 0 polls one optional flag (to extra_want) and the flags of tiles
@@ -546,26 +636,69 @@ __device__ __forceinline__ void acc_to_lds(const Acc2<R>& acc, cplx<R>* lds, boo
   }
 }
 
+// Coherent copy of the T x T tile held column-major in LDS (leading dimension
+// LDT) to the stored tile X (column-major, or row-major when rowmajor):
+// consecutive threads write consecutive 8-byte words, so every store
+// instruction covers whole cache lines.
 template <typename R, int T>
-__device__ __forceinline__ void acc_to_tile(const Acc2<R>& acc, cplx<R>* X, bool rowmajor, int rb,
-                                            int cp) {
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int b = 0; b < 2; b++) {
-    const int c = 32 * cp + 16 * b + (l & 15);
-#pragma unroll
-    for (int e = 0; e < 4; e++)
-      st_coherent(&X[tix(16 * rb + Mf<R>::row(l, e), c, T, rowmajor)],
-                  cplx<R>{acc.re[b][e], acc.im[b][e]});
+__device__ __forceinline__ void lds_to_tile(const cplx<R>* S, cplx<R>* X, bool rowmajor) {
+  typedef FGeom<T> G;
+  constexpr int WPE = sizeof(cplx<R>) / 8;  // 8-byte words per element
+  constexpr int N = T * T * WPE / G::NT;
+#pragma unroll 4
+  for (int q = 0; q < N; q++) {
+    const int wi = threadIdx.x + q * G::NT;
+    const int idx = wi / WPE, o = idx / T, i = idx % T;
+    const int e = rowmajor ? i * G::LDT + o : o * G::LDT + i;
+    if constexpr (WPE == 2) {
+      const double v = reinterpret_cast<const double*>(S)[2 * e + (wi & 1)];
+      __hip_atomic_store(reinterpret_cast<double*>(X) + wi, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      st_coherent(&X[idx], S[e]);
+    }
   }
 }
+
+// The column-major stored tile X into LDS (column-major, leading dimension LDT).
+template <typename R, int T>
+__device__ __forceinline__ void tile_to_lds(const cplx<R>* X, cplx<R>* S) {
+  typedef FGeom<T> G;
+#pragma unroll
+  for (int q = 0; q < T * T / G::NT; q++) {
+    const int idx = threadIdx.x + q * G::NT;
+    S[(idx / T) * G::LDT + idx % T] = X[idx];
+  }
+}
+
+// acc -> stored tile X through the LDS staging area `stage` (T x LDT).
+template <typename R, int T>
+__device__ __forceinline__ void stage_store(const Acc2<R>& acc, cplx<R>* stage, cplx<R>* X,
+                                            bool rowmajor, int rb, int cp) {
+  __syncthreads();  // earlier readers of the staging area are done
+  acc_to_lds<R, T>(acc, stage, false, rb, cp);
+  __syncthreads();
+  lds_to_tile<R, T>(stage, X, rowmajor);
+}
+
+// Block-inverse LU of diagonal tile s (lu_blockinv), kept beside the chain tiles.
+template <typename R, int T>
+__device__ __forceinline__ cplx<R>* lub_ptr(const FactorParams& P, int w, int s) {
+  return chain_ptr<R, T>(P, w, s, BandGeom::kChain);
+}
+
+// Diagonal flags: 1 = partial (E done), 2 = block-inverse LU published,
+// 3 = [U^-1 | L^-1] published.  Off-diagonal tiles stop at 2 (final).
+enum { FL_PARTIAL = 1, FL_FINAL = 2, FL_DIAG_INV = 3 };
 
 template <typename R, int T>
 __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
   typedef FGeom<T> G;
   constexpr int KQ = sizeof(R) == 8 ? 4 : 8;
+  constexpr int KU = (T / 4) / KQ >= 2 ? KQ : KQ / 2;  // update chunks: an even count
   extern __shared__ __align__(16) char smem_raw[];
-  cplx<R>* lds = reinterpret_cast<cplx<R>*>(smem_raw);  // T x LDT
+  cplx<R>* lds = reinterpret_cast<cplx<R>*>(smem_raw);  // T x LDT: the task's tile
+  cplx<R>* aux = lds + T * G::LDT;  // T x LDT: staging, the block-inverse LU, scratch
   __shared__ uint32_t s_ticket;
   const int B = P.g.B, NB = P.g.NB;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -588,7 +721,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
 
     // 1. the tile: the partial left by E(r, t), or generated from the stencil
     if (!early && has_early(r, t, B)) {
-      wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), 1);
+      wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), FL_PARTIAL);
 #pragma unroll
       for (int b = 0; b < 2; b++) {
         const int c = 32 * cp + 16 * b + (l & 15);
@@ -614,81 +747,78 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       }
     }
     // 2. updates A_rt -= L_rs U_st: E takes s in [mx-B, m-2], F takes s = m-1
+    // (whose inputs are final one block step before the diagonal tile m is)
     const int s_lo = early ? max(0, mx - B) : max(max(0, mx - B), m - 1);
     const int s_hi = early ? m - 2 : m - 1;
-    int* dflag = (!early && r != t) ? flag_ptr(P, w, m, m) : nullptr;
-    if (s_lo <= s_hi || dflag) wait_inputs(P, w, r, t, s_lo, s_hi, dflag, 2);
-    for (int s = s_lo; s <= s_hi; s++)
-      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, r, s), T, false, MK_NONE,
-                                tile_ptr<R, T>(P, w, s, t), T, false, MK_NONE, rb, cp);
-
+    if (s_lo <= s_hi) wait_inputs(P, w, r, t, s_lo, s_hi, nullptr, FL_FINAL);
+    update_gemms<R, T, KU>(acc, P, w, r, t, s_lo, s_hi, rb, cp);
+    acc_to_lds<R, T>(acc, lds, false, rb, cp);  // column-major in every case
     if (early) {
-      acc_to_tile<R, T>(acc, X, rowmajor, rb, cp);
-      publish(flag_ptr(P, w, r, t), 1);
+      __syncthreads();
+      lds_to_tile<R, T>(lds, X, rowmajor);
+      publish(flag_ptr(P, w, r, t), FL_PARTIAL);
       continue;
     }
     // 3. finalise
-    const cplx<R>* D = tile_ptr<R, T>(P, w, m, m);
-    if (r == t) {
-      acc_to_lds<R, T>(acc, lds, false, rb, cp);
-      __syncthreads();
-      lu_inv_tile<R, T, G::NW>(lds, G::LDT, lds + T * G::LDT, P.status);
-      for (int idx = threadIdx.x; idx < T * T; idx += G::NT)
-        st_coherent(&X[idx], lds[(idx / T) * G::LDT + idx % T]);
-    } else if (r > t) {
-      // L_rm = A_rm U_mm^-1: A from LDS (column-major), U^-1 = upper part of D
-      acc_to_lds<R, T>(acc, lds, false, rb, cp);
-      __syncthreads();
-      acc.zero();
-      tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_NONE, D, T, true, MK_UPPER, rb, cp);
-      acc_to_tile<R, T>(acc, X, false, rb, cp);
-    } else {
-      // U_mt = L_mm^-1 A_mt: L^-1 = unit-lower part of D, A from LDS (row-major)
-      acc_to_lds<R, T>(acc, lds, true, rb, cp);
-      __syncthreads();
-      acc.zero();
-      tile_gemm<R, T, KQ, false>(acc, D, T, false, MK_UNIT_LOWER, lds, G::LDT, false, MK_NONE, rb,
-                                 cp);
-      acc_to_tile<R, T>(acc, X, true, rb, cp);
-    }
-    publish(flag_ptr(P, w, r, t), 2);
-    // 4. chain tiles (off the dependency chain: published data first)
     const int d = mx - m;
+    int* dflag = flag_ptr(P, w, m, m);
     if (r == t) {
+      // LU with inverted diagonal blocks: published first (all the other
+      // finalisations of this step wait on it), then the full inverses
+      __syncthreads();
+      lu_blockinv<R, T, G::NW>(lds, G::LDT, P.status);
+      lds_to_tile<R, T>(lds, lub_ptr<R, T>(P, w, m), false);
+      publish(dflag, FL_FINAL);
+      inv_doubling<R, T, G::NW>(lds, G::LDT, aux);
+      lds_to_tile<R, T>(lds, X, false);
+      publish(dflag, FL_DIAG_INV);
+      // 4. chain tiles L_mm^-1 L_m,m-dd and U_m-dd,m U_mm^-1, with D in LDS
       for (int dd = 1; dd <= BandGeom::kChainD && dd <= B && m - dd >= 0; dd++) {
-        // L_mm^-1 L_m,m-dd and U_m-dd,m U_mm^-1, with D still in LDS
         acc.zero();
         tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_UNIT_LOWER,
                                    tile_ptr<R, T>(P, w, m, m - dd), T, true, MK_NONE, rb, cp);
-        acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_L, dd)), false, rb,
-                          cp);
+        stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_L, dd)), false,
+                          rb, cp);
         acc.zero();
         tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, m - dd, m), T, true, MK_NONE, lds,
                                    G::LDT, true, MK_UPPER, rb, cp);
-        acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_U, dd)), true, rb, cp);
+        stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_U, dd)), true,
+                          rb, cp);
       }
-    } else if (d <= BandGeom::kChainD && r > t) {
-      // L_m+d,m L_mm^-1: the new L tile (still in acc) goes to LDS
-      acc_to_lds<R, T>(acc, lds, false, rb, cp);
-      __syncthreads();
-      acc.zero();
+      continue;
+    }
+    // off-diagonal: a triangular solve with the block-inverse LU of tile m
+    wait_inputs(P, w, r, t, 0, -1, dflag, FL_FINAL);  // its barrier also covers acc_to_lds
+    tile_to_lds<R, T>(lub_ptr<R, T>(P, w, m), aux);
+    __syncthreads();
+    if (r > t)
+      trsm_right_upper<R, T>(lds, G::LDT, aux, G::LDT);  // L_rm = A_rm U_mm^-1
+    else
+      trsm_left_lower<R, T>(lds, G::LDT, aux, G::LDT);   // U_mt = L_mm^-1 A_mt
+    __syncthreads();
+    lds_to_tile<R, T>(lds, X, rowmajor);
+    publish(flag_ptr(P, w, r, t), FL_FINAL);
+    if (d > BandGeom::kChainD) continue;
+    // 4. chain tile with the full inverse D of tile m (the new tile is in LDS)
+    const cplx<R>* D = tile_ptr<R, T>(P, w, m, m);
+    wait_inputs(P, w, r, t, 0, -1, dflag, FL_DIAG_INV);
+    acc.zero();
+    if (r > t) {  // L_m+d,m L_mm^-1
       tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_NONE, D, T, true, MK_UNIT_LOWER, rb,
                                  cp);
-      acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_L, d)), true, rb, cp);
-    } else if (d <= BandGeom::kChainD) {
-      // U_mm^-1 U_m,m+d: the new U tile (still in acc) goes to LDS
-      acc_to_lds<R, T>(acc, lds, true, rb, cp);
-      __syncthreads();
-      acc.zero();
-      tile_gemm<R, T, KQ, false>(acc, D, T, false, MK_UPPER, lds, G::LDT, false, MK_NONE, rb, cp);
-      acc_to_tile<R, T>(acc, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_U, d)), false, rb, cp);
+      stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_L, d)), true, rb,
+                        cp);
+    } else {      // U_mm^-1 U_m,m+d
+      tile_gemm<R, T, KQ, false>(acc, D, T, false, MK_UPPER, lds, G::LDT, true, MK_NONE, rb, cp);
+      stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_U, d)), false, rb,
+                        cp);
     }
   }
 }
 
 template <typename R, int T>
 constexpr size_t factor_lds() {
-  return sizeof(cplx<R>) * ((size_t)T * FGeom<T>::LDT + (size_t)T * T / 2);
+  return sizeof(cplx<R>) * 2 * (size_t)T * FGeom<T>::LDT;
 }
 
 template <typename R, int T>
@@ -717,7 +847,7 @@ hipError_t prepare_factor(int T, bool fp32) {
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega, int n_omega,
                          bool fp32, void* tiles, int* flags, uint32_t* ticket, uint32_t* status,
                          int grid, hipStream_t s) {
-  const int slots = g.B >= 2 ? 4 * g.B - 2 : 3;
+  const int slots = factor_slots(g.B);
   FactorParams P{op, g, omega, n_omega, tiles, flags, ticket, status, slots,
                  (int64_t)n_omega * g.NB * slots};
   hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.tiles_per_omega(), s);

@@ -86,10 +86,13 @@ struct BandGeom {  // tile geometry of the band factor
   int B;     // tiles per half-band: ceil(b / T)
   int NB;    // block rows: ceil(n / T)
   // Block row s stores its 2B+1 band tiles (s, s-B) .. (s, s+B), then the
-  // kChain chain tiles of the solves' recurrences (rr_band.hip).
+  // kChain chain tiles of the solves' recurrences, then the diagonal tile's
+  // LU with inverted 16 x 16 diagonal blocks, read only by the
+  // factorisation itself (rr_band.hip).
   static constexpr int kChainD = 3;            // neighbour distances with chain tiles
   static constexpr int kChain = 4 * kChainD;   // chain_index() below
-  __host__ __device__ int row_tiles() const { return 2 * B + 1 + kChain; }
+  static constexpr int kAux = kChain + 1;      // tiles after the band per block row
+  __host__ __device__ int row_tiles() const { return 2 * B + 1 + kAux; }
   __host__ __device__ int64_t tiles_per_omega() const { return (int64_t)NB * row_tiles(); }
 };
 
@@ -137,6 +140,7 @@ struct SmallWs {   // workspace for tall-skinny reductions
   double* Rinv;        // n_omega * kmax*kmax complex (applied matrix)
   double* W;           // n_omega * kmax*kmax complex (SVD right vectors)
   double* Ut;          // n_omega * kmax*kmax complex (SVD left vectors)
+  double* rho;         // n_omega * 64: each column's last relative correction (refinement)
   int nchunk;
   int kmax;
 };
@@ -151,9 +155,12 @@ hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const do
 // sigma_j = ||W_j||, U_j = W_j / sigma_j  (W may alias U)
 hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, double* sigma,
                                 double* U, SmallWs& ws, uint32_t* status, hipStream_t s);
-// X += D and per-column convergence test ||D_j|| <= tol ||X_j|| (latches status)
+// X += D after correction `it` (0-based) and the per-column convergence test
+// on e_j = ||D_j|| / ||X_j||: converged when e_j <= tol or when the error left,
+// estimated as e_j times the contraction (e_j itself after the first
+// correction, e_j / e_j,prev after later ones), is below tol / 2.
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D,
-                                double tol, SmallWs& ws, uint32_t* status,
+                                double tol, int it, SmallWs& ws, uint32_t* status,
                                 uint32_t* fail_count, hipStream_t s,
                                 const uint32_t* skip = nullptr);
 // gradient kernel (rr_grad.hip)

@@ -456,7 +456,8 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
 // After X += D: a column has converged when ||D_j|| <= tol ||X_j||.  Counts
 // unconverged columns into *fail_count (reset by the caller per solve).
 __global__ void k_refine_check(int k, int nchunk, const double* px, const double* pd, double tol,
-                               uint32_t* fail_count, uint32_t* status, const uint32_t* skip) {
+                               int it, double* rho, uint32_t* fail_count, uint32_t* status,
+                               const uint32_t* skip) {
   if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const int w = blockIdx.x;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
@@ -466,12 +467,20 @@ __global__ void k_refine_check(int k, int nchunk, const double* px, const double
       sd += pd[((int64_t)w * nchunk + c) * 64 + j];
     }
     if (!isfinite(sx) || !isfinite(sd)) latch(status, ST_NONFINITE);
-    if (!(sqrt(sd) <= tol * sqrt(sx))) atomicAdd(fail_count, 1u);
+    // relative correction e and contraction estimate (refinement shrinks the
+    // error by about the same factor per correction; the first correction
+    // measures that factor as the error of the first solve)
+    const double e = sx > 0 ? sqrt(sd / sx) : (sd > 0 ? INFINITY : 0.0);
+    double* prev = rho + (int64_t)w * 64 + j;
+    const double contraction = it == 0 ? e : (*prev > 0 ? e / *prev : INFINITY);
+    *prev = e;
+    const bool ok = e <= tol || 2.0 * e * contraction <= tol;
+    if (!ok) atomicAdd(fail_count, 1u);
   }
 }
 
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D, double tol,
-                                SmallWs& ws, uint32_t* status, uint32_t* fail_count,
+                                int it, SmallWs& ws, uint32_t* status, uint32_t* fail_count,
                                 hipStream_t s, const uint32_t* skip) {
   int nc = nchunks(n);
   if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
@@ -479,8 +488,8 @@ hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const doub
   double* pd = ws.partial + (size_t)n_omega * nc * 64;
   hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
                      (double2*)X, (const double2*)D, nc, px, pd, skip);
-  hipLaunchKernelGGL(k_refine_check, dim3(n_omega), dim3(64), 0, s, k, nc, px, pd, tol,
-                     fail_count, status, skip);
+  hipLaunchKernelGGL(k_refine_check, dim3(n_omega), dim3(64), 0, s, k, nc, px, pd, tol, it,
+                     ws.rho, fail_count, status, skip);
   return hipGetLastError();
 }
 
