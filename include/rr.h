@@ -127,7 +127,8 @@ typedef struct {
                             (default 1e-10)                                     */
   double  refine_tol_sketch; /* mixed only: the same test for the sketch and
                             subspace-iteration solves, which only fix the
-                            basis Q (default 1e-8)                              */
+                            basis Q (default 1e-8).  For either tolerance a
+                            value of 1 or more means no correction at all      */
 } rr_tuning;
 
 typedef struct rr_factors rr_factors;

@@ -113,7 +113,7 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
   const bool mixed = f->prec == RR_MIXED;
   RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
                       f->xs, f->flags, ticket_word(f), st_word(f), f->solve_grid, s));
-  if (!mixed) return RR_OK;
+  if (!mixed || tol >= 1.0) return RR_OK;  // a tolerance of 1 or more asks for no correction
   double* res = f->work3;
   RR_HIP(launch_fill_u32(conv_word(f), 0u, 1, s));
   for (int it = 0; it < f->refine_iters; it++) {

@@ -122,10 +122,12 @@ __device__ __forceinline__ cplx<R> bcast(cplx<R> v, int src) {
   return cplx<R>{bcast(v.re, src), bcast(v.im, src)};
 }
 
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <typename R>
 __device__ __forceinline__ void csub_mul(cplx<R>& x, cplx<R> a, cplx<R> b) {  // x -= a b
-  x.re -= a.re * b.re - a.im * b.im;
-  x.im -= a.re * b.im + a.im * b.re;
+  x.re = fmaR(-a.re, b.re, fmaR(a.im, b.im, x.re));
+  x.im = fmaR(-a.re, b.im, fmaR(-a.im, b.re, x.im));
 }
 
 // (re, im) (+/-)= A * B for one 16 x 16 output block with K = 4q terms, both
@@ -175,62 +177,6 @@ __device__ __forceinline__ void blk_store(const typename Mf<R>::v4& re,
 // 16 .. 63 compute copies and store nothing.  The other triangle of the block is
 // neither read nor written, so the L and U inversions of one block may run
 // in two waves at once.
-// z unchanged, but the compiler must take it as computed from v as well:
-// loads addressed with it wait for v, which keeps them from being hoisted
-// ahead of the values they are used with (register pressure).
-__device__ __forceinline__ int zero_after(int z, float v) {
-  asm volatile("" : "=v"(z) : "0"(z), "v"(v));
-  return z;
-}
-__device__ __forceinline__ int zero_after(int z, double v) {
-  asm volatile("" : "=v"(z) : "0"(z), "v"(v));
-  return z;
-}
-
-template <typename R>
-__device__ __forceinline__ void inv_diag16(cplx<R>* S, int LD, int b0, bool isL) {
-  const int lane = threadIdx.x & 63, c = lane & 15;
-  cplx<R> x[16];
-#pragma unroll
-  for (int i = 0; i < 16; i++) x[i] = cplx<R>{i == c ? (R)1 : (R)0, (R)0};
-  // column-oriented substitution: once x_j is final it is eliminated from the
-  // rows still open; column j of the triangle is loaded only after column
-  // j - 1 is done (z), so one column is live at a time
-  int z = 0;
-  if (isL) {
-#pragma unroll
-    for (int j = 0; j < 15; j++) {
-      const cplx<R>* col = S + (b0 + j) * LD + b0 + z;
-#pragma unroll
-      for (int i = j + 1; i < 16; i++) {
-        csub_mul(x[i], col[i], x[j]);
-        z = zero_after(z, x[i].re);
-      }
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int i = 1; i < 16; i++)
-        if (i > c) S[(b0 + c) * LD + b0 + i] = x[i];
-    }
-  } else {
-#pragma unroll
-    for (int j = 15; j >= 0; j--) {
-      const cplx<R>* col = S + (b0 + j) * LD + b0 + z;
-      x[j] = cmul(x[j], cinv(col[j]));
-#pragma unroll
-      for (int i = 0; i < j; i++) {
-        csub_mul(x[i], col[i], x[j]);
-        z = zero_after(z, x[i].re);
-      }
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; i++)
-        if (i <= c) S[(b0 + c) * LD + b0 + i] = x[i];
-    }
-  }
-}
-
 // No-pivot LU of the T x T tile S (LDS, column-major, leading dimension LD),
 // then in-place inversion of its 16 x 16 diagonal blocks:
 //   S <- L (strictly lower, unit diagonal implied) and U (upper, diagonal
@@ -238,9 +184,9 @@ __device__ __forceinline__ void inv_diag16(cplx<R>* S, int LD, int b0, bool isL)
 // (the block-inverse LU: enough for the triangular solves of the
 // off-diagonal finalisations).  Blocked so that the sequential part is short
 // and wave-local: per 16-column panel one wave factors the panel in registers
-// (lane = row, the pivot row broadcast lane to lane), then U12 = L11^-1 A12 by
-// forward substitution (thread = column, in registers), then A22 -= L21 U12
-// on MFMA; the diagonal blocks are inverted by substitution (inv_diag16).
+// (lane = row, the pivot row broadcast lane to lane); then U12 = L11^-1 A12
+// and L11^-1 by forward substitution (thread = column, in registers) while
+// another wave forms U11^-1 by back substitution; then A22 -= L21 U12 on MFMA.
 // A zero or non-finite pivot latches ST_SINGULAR and is replaced by 1.
 template <typename R, int T, int NW>
 __device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
@@ -251,7 +197,8 @@ __device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
   auto at = [&](int i, int c) -> cplx<R>& { return S[c * LD + i]; };
 #pragma unroll 1
   for (int c0 = 0; c0 < T; c0 += P) {
-    // panel: lane = row c0 + lane
+    // panel: lane = row c0 + lane.  Lanes at or above the pivot row get a
+    // zero multiplier, which leaves their row unchanged (no per-element select).
     if (wave == 0) {
       const int r = c0 + lane;
       const bool act = r < T;
@@ -267,14 +214,11 @@ __device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
           if (lane == j) a[j] = one;
           p = one;
         }
-        const cplx<R> l = cmul(a[j], cinv(p));
         const bool below = act && lane > j;
+        const cplx<R> l = below ? cmul(a[j], cinv(p)) : zero;
         if (below) a[j] = l;
 #pragma unroll
-        for (int c = j + 1; c < P; c++) {
-          const cplx<R> u = bcast(a[c], j);
-          if (below) csub_mul(a[c], l, u);
-        }
+        for (int c = j + 1; c < P; c++) csub_mul(a[c], l, bcast(a[c], j));
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
@@ -282,25 +226,55 @@ __device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
         if (act) at(r, c0 + c) = a[c];
     }
     __syncthreads();
-    if (c0 + P >= T) break;
-    // U12 = L11^-1 A12: thread t owns column c0 + P + t
-    if (threadIdx.x < T - c0 - P) {
-      const int c = c0 + P + threadIdx.x;
-      cplx<R> x[P];
+    // Wave 0: U12 = L11^-1 A12 by forward substitution, thread t owning
+    // column c0 + P + t, and L11^-1 in the next 16 threads (identity columns).
+    // Wave 1: U11^-1 by back substitution, lane t < 16 owning column t.
+    // Both inverses are kept in registers until the barrier (L11 and U11
+    // are read until then) and written over the diagonal block after it.
+    const int nu = T - c0 - P;  // columns of U12
+    cplx<R> x[P];
+    const bool lsolve = threadIdx.x < nu + P;
+    const bool uinv = wave == 1 && lane < P;
+    if (lsolve) {
+      const int t = threadIdx.x;
 #pragma unroll
-      for (int i = 0; i < P; i++) x[i] = at(c0 + i, c);
+      for (int i = 0; i < P; i++)
+        x[i] = t < nu ? at(c0 + i, c0 + P + t) : cplx<R>{i == t - nu ? (R)1 : (R)0, (R)0};
 #pragma unroll
       for (int j = 0; j < P - 1; j++) {
 #pragma unroll
         for (int i = j + 1; i < P; i++) csub_mul(x[i], at(c0 + i, c0 + j), x[j]);
         __builtin_amdgcn_sched_barrier(0);
       }
+      if (t < nu) {
 #pragma unroll
-      for (int i = 0; i < P; i++) at(c0 + i, c) = x[i];
+        for (int i = 0; i < P; i++) at(c0 + i, c0 + P + t) = x[i];
+      }
+    } else if (uinv) {
+#pragma unroll
+      for (int i = 0; i < P; i++) x[i] = cplx<R>{i == lane ? (R)1 : (R)0, (R)0};
+#pragma unroll
+      for (int j = P - 1; j >= 0; j--) {
+        x[j] = cmul(x[j], cinv(at(c0 + j, c0 + j)));
+#pragma unroll
+        for (int i = 0; i < j; i++) csub_mul(x[i], at(c0 + i, c0 + j), x[j]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     __syncthreads();
-    // A22 -= L21 U12 in 16 x 16 blocks
-    const int nb = (T - c0 - P) / 16;
+    if (lsolve && threadIdx.x >= nu) {  // L11^-1, strictly lower part
+      const int cc = threadIdx.x - nu;
+#pragma unroll
+      for (int i = 1; i < P; i++)
+        if (i > cc) at(c0 + i, c0 + cc) = x[i];
+    } else if (uinv) {                  // U11^-1, upper part with the diagonal
+#pragma unroll
+      for (int i = 0; i < P; i++)
+        if (i <= lane) at(c0 + i, c0 + lane) = x[i];
+    }
+    if (nu == 0) break;
+    // A22 -= L21 U12 in 16 x 16 blocks (disjoint from the diagonal block)
+    const int nb = nu / 16;
     for (int b = wave; b < nb * nb; b += NW) {
       const int bi = c0 + P + 16 * (b % nb), bj = c0 + P + 16 * (b / nb);
       v4 re, im;
@@ -310,11 +284,6 @@ __device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
     }
     __syncthreads();
   }
-  // inverses of the 16 x 16 diagonal blocks, in place, one wave per block
-  // (tasks 0 .. T/16-1: L blocks, the rest U blocks)
-  constexpr int NDB = T / 16;
-  for (int tsk = wave; tsk < 2 * NDB; tsk += NW)
-    inv_diag16<R>(S, LD, 16 * (tsk < NDB ? tsk : tsk - NDB), tsk < NDB);
   __syncthreads();
 }
 
