@@ -457,16 +457,16 @@ __host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B - 2 :
 
 __device__ __forceinline__ Task decode(int slot, int m, int B) {
   if (slot == 0) return {0, m, m};
-  if (slot == 1) return {0, m + 1, m};
-  if (slot == 2) return {0, m, m + 1};
-  if (B < 2) return {0, -1, -1};
-  int e = slot - 3;
+  if (B < 2) return slot == 1 ? Task{0, m + 1, m} : Task{0, m, m + 1};
+  int e = slot - 1;
   if (e < 2 * B - 3) {
     int mm = m + 1;
     if (e == 0) return {1, mm, mm};
     int d = (e + 1) >> 1;
     return (e & 1) ? Task{1, mm + d, mm} : Task{1, mm, mm + d};
   }
+  if (slot == 2 * B - 2) return {0, m + 1, m};
+  if (slot == 2 * B - 1) return {0, m, m + 1};
   int f = slot - 2 * B;
   int d = 2 + (f >> 1);
   return (f & 1) ? Task{0, m, m + d} : Task{0, m + d, m};
@@ -543,36 +543,44 @@ __device__ __forceinline__ void update_gemms(Acc2<R>& acc, const FactorParams& P
   }
 }
 
-// Thread 0 polls one optional flag (to extra_want) and the flags of tiles
-// (r, s) and (s, t), s in [s0, s1] (to 2 = final), then one acquire fence.
+// Wave 0 polls one optional flag (to extra_want) and the flags of tiles
+// (r, s) and (s, t), s in [s0, s1] (to 2 = final), one flag per lane so that
+// the round trips of the atomic polls overlap (lane q takes flags q, q + 64,
+// ...), then lane 0 issues one acquire fence and the barrier hands the result
+// to every wave.
 __device__ __forceinline__ void wait_inputs(const FactorParams& P, int w, int r, int t, int s0,
                                             int s1, int* extra, int extra_want) {
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int nq = 1 + 2 * max(0, s1 - s0 + 1);  // q = 0: extra, then (r, s), (s, t) pairs
     bool live =
         !(__hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT);
     uint64_t t0 = wall_clock64();
     uint32_t polls = 0;
-    for (int q = -1; q < 2 * (s1 - s0 + 1); q++) {
-      int* f;
+    for (int q0 = 0; q0 < nq; q0 += 64) {
+      const int q = q0 + lane;
+      int* f = nullptr;
       int want = 2;
-      if (q < 0) {
-        if (!extra) continue;
+      if (q == 0) {
         f = extra;
         want = extra_want;
-      } else {
-        int s = s0 + (q >> 1);
-        f = (q & 1) ? flag_ptr(P, w, s, t) : flag_ptr(P, w, r, s);
+      } else if (q < nq) {
+        const int s = s0 + ((q - 1) >> 1);
+        f = ((q - 1) & 1) ? flag_ptr(P, w, s, t) : flag_ptr(P, w, r, s);
       }
-      while (live &&
-             __hip_atomic_fetch_add(f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+      bool done = f == nullptr;
+      for (;;) {
+        if (!done)
+          done = __hip_atomic_fetch_add(f, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+        if (__all(done) || !live) break;
         __builtin_amdgcn_s_sleep(1);
         if (++polls > kWaitPolls || wall_clock64() - t0 > kWaitTicks) {
-          latch(P.status, ST_TIMEOUT);
+          if (lane == 0) latch(P.status, ST_TIMEOUT);
           live = false;
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (lane == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }

@@ -22,7 +22,10 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
 }
 
 // partial[w][chunk] = (Y_c T)^H (Y_c T) over the chunk's rows, where T is the
-// k x k matrix Tm[w] (identity when Tm == NULL).  Y: (n_omega, k, n).
+// k x k matrix Tm[w] (identity when Tm == NULL).  Y: (n_omega, k, n).  Thread
+// t accumulates the 2 x 2 group of entries (2 t/16 .. +1, 2 (t%16) .. +1) on
+// and above the diagonal (the Cholesky reads the upper triangle only); the
+// sketch width is at most KM = 32, so 256 threads cover every group.
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const double2* __restrict__ Y,
                                                       const double2* __restrict__ Tm, int kmax,
                                                       int nchunk, double2* __restrict__ partial) {
@@ -34,49 +37,62 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const do
     for (int idx = threadIdx.x; idx < k * k; idx += 256)
       tm[idx / k][idx % k] = Tm[(int64_t)w * kmax * kmax + idx];  // tm[i][j] = T[i][j]
   }
-  const int npairs = k * k;
-  double2 acc[4];
-  for (int q = 0; q < 4; q++) acc[q] = make_double2(0, 0);
+  const int i0 = 2 * (threadIdx.x / 16), j0 = 2 * (threadIdx.x % 16);
+  const bool act = i0 < k && j0 < k && j0 + 1 >= i0;
+  double2 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int c = 0; c < 2; c++) acc[a][c] = make_double2(0, 0);
   int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
   for (int64_t rb = r0; rb < r1; rb += kSub) {
     int rows = (int)min((int64_t)kSub, r1 - rb);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kSub * k; idx += 256) {
+    for (int idx = threadIdx.x; idx < kSub * KM; idx += 256) {
       int j = idx / kSub, rr = idx % kSub;
-      ys[rr][j] = rr < rows ? Yw[(int64_t)j * n + rb + rr] : make_double2(0, 0);
+      ys[rr][j] = (rr < rows && j < k) ? Yw[(int64_t)j * n + rb + rr] : make_double2(0, 0);
     }
     __syncthreads();
-    if (Tm) {  // ys <- ys * T, one row per thread
-      double2 tmp[KM];
-      for (int rr = threadIdx.x; rr < kSub; rr += 256) {
+    if (Tm) {  // ys <- ys * T, one row per thread (the row held in registers)
+      if (threadIdx.x < kSub) {
+        const int rr = threadIdx.x;
+        double2 row[KM];
+#pragma unroll
+        for (int i = 0; i < KM; i++) row[i] = ys[rr][i];
         for (int j = 0; j < k; j++) {
           double2 s = make_double2(0, 0);
-          for (int i = 0; i < k; i++) {
-            double2 p = cmul(ys[rr][i], tm[i][j]);
-            s.x += p.x; s.y += p.y;
+#pragma unroll
+          for (int i = 0; i < KM; i++) {
+            if (i < k) {
+              double2 p = cmul(row[i], tm[i][j]);
+              s.x += p.x; s.y += p.y;
+            }
           }
-          tmp[j] = s;
+          ys[rr][j] = s;
         }
-        for (int j = 0; j < k; j++) ys[rr][j] = tmp[j];
       }
       __syncthreads();
     }
-    for (int q = 0; q < 4; q++) {
-      int pr = threadIdx.x + 256 * q;
-      if (pr >= npairs) break;
-      int i = pr / k, j = pr % k;
-      double2 s = acc[q];
+    if (act) {
       for (int rr = 0; rr < rows; rr++) {
-        double2 p = cmulc(ys[rr][i], ys[rr][j]);
-        s.x += p.x; s.y += p.y;
+        const double2 a0 = ys[rr][i0], a1 = ys[rr][i0 + 1];
+        const double2 b0 = ys[rr][j0], b1 = ys[rr][j0 + 1];
+        double2 p;
+        p = cmulc(a0, b0); acc[0][0].x += p.x; acc[0][0].y += p.y;
+        p = cmulc(a0, b1); acc[0][1].x += p.x; acc[0][1].y += p.y;
+        p = cmulc(a1, b0); acc[1][0].x += p.x; acc[1][0].y += p.y;
+        p = cmulc(a1, b1); acc[1][1].x += p.x; acc[1][1].y += p.y;
       }
-      acc[q] = s;
     }
   }
-  for (int q = 0; q < 4; q++) {
-    int pr = threadIdx.x + 256 * q;
-    if (pr >= npairs) break;
-    partial[((int64_t)w * nchunk + chunk) * kmax * kmax + pr] = acc[q];
+  if (act) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int c = 0; c < 2; c++)
+        if (i0 + a < k && j0 + c < k)
+          partial[((int64_t)w * nchunk + chunk) * kmax * kmax + (i0 + a) * k + j0 + c] =
+              acc[a][c];
   }
 }
 
@@ -91,11 +107,13 @@ __global__ __launch_bounds__(256) void k_chol(int k, int kmax, int nchunk,
   __shared__ double2 Ri[KM][KM + 1];
   __shared__ int bad;
   const int w = blockIdx.x;
-  for (int pr = threadIdx.x; pr < k * k; pr += 256) {
+  for (int pr = threadIdx.x; pr < k * k; pr += 256) {  // upper triangle (all that is used)
     double2 s = make_double2(0, 0);
-    for (int c = 0; c < nchunk; c++) {
-      double2 v = partial[((int64_t)w * nchunk + c) * kmax * kmax + pr];
-      s.x += v.x; s.y += v.y;
+    if (pr % k >= pr / k) {
+      for (int c = 0; c < nchunk; c++) {
+        double2 v = partial[((int64_t)w * nchunk + c) * kmax * kmax + pr];
+        s.x += v.x; s.y += v.y;
+      }
     }
     G[pr / k][pr % k] = s;
   }
@@ -177,7 +195,8 @@ __global__ __launch_bounds__(256) void k_chol(int k, int kmax, int nchunk,
   if (threadIdx.x == 0 && bad) latch(status, ST_BREAKDOWN);
 }
 
-// Out = Y * Tm[w]  (n x k times k x k), one row per thread; Out may alias Y.
+// Out = Y * Tm[w]  (n x k times k x k), one row per thread (held in registers);
+// Out may alias Y.
 __global__ __launch_bounds__(256) void k_apply_small(int64_t n, int k, const double2* Y,
                                                      const double2* __restrict__ Tm, int kmax,
                                                      double2* Out) {
@@ -191,12 +210,16 @@ __global__ __launch_bounds__(256) void k_apply_small(int64_t n, int k, const dou
   const double2* Yw = Y + (int64_t)w * k * n;
   double2* Ow = Out + (int64_t)w * k * n;
   double2 row[KM];
-  for (int i = 0; i < k; i++) row[i] = Yw[(int64_t)i * n + r];
+#pragma unroll
+  for (int i = 0; i < KM; i++) row[i] = i < k ? Yw[(int64_t)i * n + r] : make_double2(0, 0);
   for (int j = 0; j < k; j++) {
     double2 s = make_double2(0, 0);
-    for (int i = 0; i < k; i++) {
-      double2 p = cmul(row[i], tm[i][j]);
-      s.x += p.x; s.y += p.y;
+#pragma unroll
+    for (int i = 0; i < KM; i++) {
+      if (i < k) {
+        double2 p = cmul(row[i], tm[i][j]);
+        s.x += p.x; s.y += p.y;
+      }
     }
     Ow[(int64_t)j * n + r] = s;
   }
