@@ -88,6 +88,8 @@ uint32_t* st_word(rr_factors* f) { return f->ctrl; }
 uint32_t* ticket_word(rr_factors* f) { return f->ctrl + 1; }
 uint32_t* fail_word(rr_factors* f) { return f->ctrl + 2; }
 uint32_t* conv_word(rr_factors* f) { return f->ctrl + 3; }
+// ctrl[20], ctrl[21]: the factorisation's task tickets and diagonal-worker roles
+uint32_t* factor_counters(rr_factors* f) { return f->ctrl + 20; }
 // ctrl[4 + it]: unconverged columns after correction it (mixed solves)
 constexpr int kMaxRefine = 16;
 
@@ -360,7 +362,7 @@ rr_status rr_refactor(rr_factors* f, void* stream) {
   if (!f) return fail(RR_ERR_INVALID, "NULL handle");
   if (f->sticky_hip_error) return fail(RR_ERR_HIP, "handle is unusable after a HIP error");
   hipError_t e = launch_factor(opdesc(f), f->geom, f->omega, f->n_omega, f->prec == RR_MIXED,
-                               f->tiles, f->flags, ticket_word(f), st_word(f), f->grid,
+                               f->tiles, f->flags, factor_counters(f), st_word(f), f->grid,
                                (hipStream_t)stream);
   if (e != hipSuccess) {
     f->sticky_hip_error = true;

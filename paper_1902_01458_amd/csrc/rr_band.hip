@@ -69,7 +69,7 @@ struct FactorParams {
   int n_omega;
   void* tiles;
   int* flags;           // per tile: 1 = partial (E done), 2 = final
-  uint32_t* ticket;
+  uint32_t* ticket;     // [0] task tickets, [1] diagonal-worker roles
   uint32_t* status;
   int slots;            // tickets per step and shift
   int64_t total;        // n_omega * NB * slots
@@ -443,33 +443,47 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
   }
 }
 
-// Task decoding: slot -> (kind, r, t) for step m.  kind 0 = F, 1 = E.
-//   slot 0: F(m, m); 1: F(m+1, m); 2: F(m, m+1)
-//   slots 3 .. 2B-1: E of the tiles finalised at step m+1 (distance <= B-2)
-//   slots 2B .. 4B-3: F at distance 2 .. B
-// (Issuing F(m+1, m+1) early, right after its inputs, measured slower: its
-// workgroup then waits a whole step and the other tasks start later.)
+// The diagonal tiles are not in the ticket order: the first n_omega
+// workgroups to start (a second counter) each own the diagonal chain of one
+// shift and factor its diagonal tiles m = 0, 1, ... in turn, so a diagonal
+// step starts the moment its inputs are final instead of when a workgroup
+// frees up for its ticket.  Its inputs all come from earlier block steps of
+// the ticket order (below), so a ticket task waiting on a diagonal tile
+// cannot block it.
+//
+// Task decoding: slot -> (kind, r, t) for block step m.  Kinds: 0 = F,
+// 1 = E, 2 / 3 = the chain tiles of diagonal tile m (column / row side).
+//   slots 0 .. 2B-4: E of the tiles finalised at step m+1 (distance <= B-2),
+//     E(m+1, m+1) first (it feeds the next diagonal tile)
+//   slots 2B-3, 2B-2: F(m+1, m), F(m, m+1)
+//   slots 2B-1 .. 4B-4: F at distance 2 .. B
+//   slots 4B-3, 4B-2: the chain tiles of diagonal tile m
+// (B = 1: F(m+1, m), F(m, m+1) and the two chain tasks.)
 struct Task {
   int kind, r, t;
 };
 
-__host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B - 2 : 3; }
+__host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B - 1 : 4; }
 
 __device__ __forceinline__ Task decode(int slot, int m, int B) {
-  if (slot == 0) return {0, m, m};
-  if (B < 2) return slot == 1 ? Task{0, m + 1, m} : Task{0, m, m + 1};
-  int e = slot - 1;
-  if (e < 2 * B - 3) {
-    int mm = m + 1;
-    if (e == 0) return {1, mm, mm};
-    int d = (e + 1) >> 1;
-    return (e & 1) ? Task{1, mm + d, mm} : Task{1, mm, mm + d};
+  if (B < 2) {
+    if (slot == 0) return {0, m + 1, m};
+    if (slot == 1) return {0, m, m + 1};
+    return {slot == 2 ? 2 : 3, m, m};
   }
-  if (slot == 2 * B - 2) return {0, m + 1, m};
-  if (slot == 2 * B - 1) return {0, m, m + 1};
-  int f = slot - 2 * B;
-  int d = 2 + (f >> 1);
-  return (f & 1) ? Task{0, m, m + d} : Task{0, m + d, m};
+  if (slot < 2 * B - 3) {
+    const int mm = m + 1;
+    if (slot == 0) return {1, mm, mm};
+    const int d = (slot + 1) >> 1;
+    return (slot & 1) ? Task{1, mm + d, mm} : Task{1, mm, mm + d};
+  }
+  if (slot == 2 * B - 3) return {0, m + 1, m};
+  if (slot == 2 * B - 2) return {0, m, m + 1};
+  if (slot < 4 * B - 3) {
+    const int f = slot - (2 * B - 1), d = 2 + (f >> 1);
+    return (f & 1) ? Task{0, m, m + d} : Task{0, m + d, m};
+  }
+  return {slot == 4 * B - 3 ? 2 : 3, m, m};
 }
 
 // E(r, t) has work when its early range s in [mx-B, m-2] is non-empty.
@@ -668,6 +682,42 @@ __device__ __forceinline__ cplx<R>* lub_ptr(const FactorParams& P, int w, int s)
 // 3 = [U^-1 | L^-1] published.  Off-diagonal tiles stop at 2 (final).
 enum { FL_PARTIAL = 1, FL_FINAL = 2, FL_DIAG_INV = 3 };
 
+// The tile (r, t) into the accumulators: the partial left by E(r, t), or
+// generated from the stencil.
+template <typename R, int T>
+__device__ __forceinline__ void load_tile(const FactorParams& P, Acc2<R>& acc, int w, int r,
+                                          int t, bool early, int rb, int cp) {
+  const int l = threadIdx.x & 63;
+  const bool rowmajor = r < t;
+  if (!early && has_early(r, t, P.g.B)) {
+    const cplx<R>* X = tile_ptr<R, T>(P, w, r, t);
+    wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), FL_PARTIAL);
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int c = 32 * cp + 16 * b + (l & 15);
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        cplx<R> v = X[tix(16 * rb + Mf<R>::row(l, e), c, T, rowmajor)];
+        acc.re[b][e] = v.re;
+        acc.im[b][e] = v.im;
+      }
+    }
+  } else {
+    const double om_r = P.omega[2 * w], om_i = P.omega[2 * w + 1];
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int c = 32 * cp + 16 * b + (l & 15);
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        double2 v = m_entry(P.op, om_r, om_i, (int64_t)r * T + 16 * rb + Mf<R>::row(l, e),
+                            (int64_t)t * T + c);
+        acc.re[b][e] = (R)v.x;
+        acc.im[b][e] = (R)v.y;
+      }
+    }
+  }
+}
+
 template <typename R, int T>
 __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
   typedef FGeom<T> G;
@@ -678,9 +728,35 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
   cplx<R>* aux = lds + T * G::LDT;  // T x LDT: staging, the block-inverse LU, scratch
   __shared__ uint32_t s_ticket;
   const int B = P.g.B, NB = P.g.NB;
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   const int rb = wave / G::CPR, cp = wave % G::CPR;
   Acc2<R> acc;
+
+  // diagonal worker of shift w: F(m, m) for m = 0 .. NB-1
+  const int64_t role = wg_ticket(P.ticket + 1, &s_ticket);
+  if (role < P.n_omega) {
+    const int w = (int)role;
+#pragma unroll 1
+    for (int m = 0; m < NB; m++) {
+      cplx<R>* X = tile_ptr<R, T>(P, w, m, m);
+      int* dflag = flag_ptr(P, w, m, m);
+      load_tile<R, T>(P, acc, w, m, m, false, rb, cp);
+      if (m >= 1) wait_inputs(P, w, m, m, m - 1, m - 1, nullptr, FL_FINAL);
+      update_gemms<R, T, KU>(acc, P, w, m, m, max(0, m - 1), m - 1, rb, cp);
+      acc_to_lds<R, T>(acc, lds, false, rb, cp);
+      __syncthreads();
+      // LU with inverted diagonal blocks: published first (the step's other
+      // finalisations wait on it), then the full inverses
+      lu_blockinv<R, T, G::NW>(lds, G::LDT, P.status);
+      lds_to_tile<R, T>(lds, lub_ptr<R, T>(P, w, m), false);
+      publish(dflag, FL_FINAL);
+      inv_doubling<R, T, G::NW>(lds, G::LDT, aux);
+      lds_to_tile<R, T>(lds, X, false);
+      publish(dflag, FL_DIAG_INV);
+    }
+    return;
+  }
+
   for (;;) {
     const int64_t ticket = wg_ticket(P.ticket, &s_ticket);
     if (ticket >= P.total) break;
@@ -690,41 +766,38 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     const Task tk = decode(slot, m0, B);
     const int r = tk.r, t = tk.t;
     if (r < 0 || r >= NB || t >= NB) continue;
+    const int m = min(r, t), mx = max(r, t);
+    int* dflag = flag_ptr(P, w, m, m);
+    if (tk.kind >= 2) {
+      // chain tiles of diagonal tile m: L_mm^-1 L_m,m-dd (kind 2) or
+      // U_m-dd,m U_mm^-1 (kind 3), dd = 1 .. kChainD, with D_m in LDS
+      if (m == 0) continue;
+      wait_inputs(P, w, m, m, 0, -1, dflag, FL_DIAG_INV);
+      tile_to_lds<R, T>(tile_ptr<R, T>(P, w, m, m), lds);
+      __syncthreads();
+      for (int dd = 1; dd <= BandGeom::kChainD && dd <= B && m - dd >= 0; dd++) {
+        acc.zero();
+        if (tk.kind == 2) {
+          tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_UNIT_LOWER,
+                                     tile_ptr<R, T>(P, w, m, m - dd), T, true, MK_NONE, rb, cp);
+          stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_L, dd)),
+                            false, rb, cp);
+        } else {
+          tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, m - dd, m), T, true, MK_NONE, lds,
+                                     G::LDT, true, MK_UPPER, rb, cp);
+          stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_U, dd)), true,
+                            rb, cp);
+        }
+      }
+      continue;
+    }
     const bool early = tk.kind == 1;
     if (early && !has_early(r, t, B)) continue;
-    const int m = min(r, t), mx = max(r, t);
     const bool rowmajor = r < t;  // U tiles
     cplx<R>* X = tile_ptr<R, T>(P, w, r, t);
-
-    // 1. the tile: the partial left by E(r, t), or generated from the stencil
-    if (!early && has_early(r, t, B)) {
-      wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), FL_PARTIAL);
-#pragma unroll
-      for (int b = 0; b < 2; b++) {
-        const int c = 32 * cp + 16 * b + (l & 15);
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          cplx<R> v = X[tix(16 * rb + Mf<R>::row(l, e), c, T, rowmajor)];
-          acc.re[b][e] = v.re;
-          acc.im[b][e] = v.im;
-        }
-      }
-    } else {
-      const double om_r = P.omega[2 * w], om_i = P.omega[2 * w + 1];
-#pragma unroll
-      for (int b = 0; b < 2; b++) {
-        const int c = 32 * cp + 16 * b + (l & 15);
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          double2 v = m_entry(P.op, om_r, om_i, (int64_t)r * T + 16 * rb + Mf<R>::row(l, e),
-                              (int64_t)t * T + c);
-          acc.re[b][e] = (R)v.x;
-          acc.im[b][e] = (R)v.y;
-        }
-      }
-    }
-    // 2. updates A_rt -= L_rs U_st: E takes s in [mx-B, m-2], F takes s = m-1
-    // (whose inputs are final one block step before the diagonal tile m is)
+    // 1. the tile; 2. updates A_rt -= L_rs U_st: E takes s in [mx-B, m-2],
+    // F takes s = m-1 (whose inputs are final a block step before tile m is)
+    load_tile<R, T>(P, acc, w, r, t, early, rb, cp);
     const int s_lo = early ? max(0, mx - B) : max(max(0, mx - B), m - 1);
     const int s_hi = early ? m - 2 : m - 1;
     if (s_lo <= s_hi) wait_inputs(P, w, r, t, s_lo, s_hi, nullptr, FL_FINAL);
@@ -736,35 +809,8 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       publish(flag_ptr(P, w, r, t), FL_PARTIAL);
       continue;
     }
-    // 3. finalise
+    // 3. finalise: a triangular solve with the block-inverse LU of tile m
     const int d = mx - m;
-    int* dflag = flag_ptr(P, w, m, m);
-    if (r == t) {
-      // LU with inverted diagonal blocks: published first (all the other
-      // finalisations of this step wait on it), then the full inverses
-      __syncthreads();
-      lu_blockinv<R, T, G::NW>(lds, G::LDT, P.status);
-      lds_to_tile<R, T>(lds, lub_ptr<R, T>(P, w, m), false);
-      publish(dflag, FL_FINAL);
-      inv_doubling<R, T, G::NW>(lds, G::LDT, aux);
-      lds_to_tile<R, T>(lds, X, false);
-      publish(dflag, FL_DIAG_INV);
-      // 4. chain tiles L_mm^-1 L_m,m-dd and U_m-dd,m U_mm^-1, with D in LDS
-      for (int dd = 1; dd <= BandGeom::kChainD && dd <= B && m - dd >= 0; dd++) {
-        acc.zero();
-        tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_UNIT_LOWER,
-                                   tile_ptr<R, T>(P, w, m, m - dd), T, true, MK_NONE, rb, cp);
-        stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_L, dd)), false,
-                          rb, cp);
-        acc.zero();
-        tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, m - dd, m), T, true, MK_NONE, lds,
-                                   G::LDT, true, MK_UPPER, rb, cp);
-        stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_ADJ_U, dd)), true,
-                          rb, cp);
-      }
-      continue;
-    }
-    // off-diagonal: a triangular solve with the block-inverse LU of tile m
     wait_inputs(P, w, r, t, 0, -1, dflag, FL_FINAL);  // its barrier also covers acc_to_lds
     tile_to_lds<R, T>(lub_ptr<R, T>(P, w, m), aux);
     __syncthreads();
@@ -821,24 +867,38 @@ hipError_t prepare_factor(int T, bool fp32) {
   return hipErrorInvalidValue;
 }
 
+// Shifts per launch: every shift of a launch holds one diagonal worker for the
+// whole launch, so their number stays well below the resident workgroups (one
+// per CU) and more shifts are factored by consecutive launches.
+constexpr int kMaxShiftsPerLaunch = 64;
+
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega, int n_omega,
-                         bool fp32, void* tiles, int* flags, uint32_t* ticket, uint32_t* status,
-                         int grid, hipStream_t s) {
+                         bool fp32, void* tiles, int* flags, uint32_t* counters,
+                         uint32_t* status, int grid, hipStream_t s) {
   const int slots = factor_slots(g.B);
-  FactorParams P{op, g, omega, n_omega, tiles, flags, ticket, status, slots,
-                 (int64_t)n_omega * g.NB * slots};
+  const size_t tile_bytes = (size_t)g.T * g.T * (fp32 ? 8 : 16);
   hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.tiles_per_omega(), s);
-  if (e == hipSuccess) e = launch_fill_u32(ticket, 0u, 1, s);
-  if (e != hipSuccess) return e;
-  if (grid > P.total) grid = (int)P.total;
-  if (fp32) {
-    if (g.T == 64) return launch_factor_t<float, 64>(P, grid, s);
-    if (g.T == 32) return launch_factor_t<float, 32>(P, grid, s);
-  } else {
-    if (g.T == 64) return launch_factor_t<double, 64>(P, grid, s);
-    if (g.T == 32) return launch_factor_t<double, 32>(P, grid, s);
+  for (int w0 = 0; e == hipSuccess && w0 < n_omega; w0 += kMaxShiftsPerLaunch) {
+    const int nw = n_omega - w0 < kMaxShiftsPerLaunch ? n_omega - w0 : kMaxShiftsPerLaunch;
+    FactorParams P{op, g, omega + 2 * w0, nw,
+                   static_cast<char*>(tiles) + (size_t)w0 * g.tiles_per_omega() * tile_bytes,
+                   flags + (size_t)w0 * g.NB * (2 * g.B + 1), counters, status, slots,
+                   (int64_t)nw * g.NB * slots};
+    e = launch_fill_u32(counters, 0u, 2, s);  // tickets and worker roles
+    if (e != hipSuccess) break;
+    int gr = grid > P.total ? (int)P.total : grid;
+    gr += nw;  // the diagonal workers
+    if (fp32) {
+      if (g.T == 64) e = launch_factor_t<float, 64>(P, gr, s);
+      else if (g.T == 32) e = launch_factor_t<float, 32>(P, gr, s);
+      else e = hipErrorInvalidValue;
+    } else {
+      if (g.T == 64) e = launch_factor_t<double, 64>(P, gr, s);
+      else if (g.T == 32) e = launch_factor_t<double, 32>(P, gr, s);
+      else e = hipErrorInvalidValue;
+    }
   }
-  return hipErrorInvalidValue;
+  return e;
 }
 
 }  // namespace rr

@@ -115,9 +115,11 @@ hipError_t launch_apply(const OpDesc& op, const double* omega /*dev 2*n_omega*/,
 hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed,
                          double* Theta, hipStream_t s);
 
-// Band LU: tiles = n_omega * NB * (2B+1) tiles of T*T complex (R = float|double)
+// Band LU: tiles = n_omega * tiles_per_omega() tiles of T*T complex (R = float|double).
+// counters: two device words (task tickets, diagonal-worker roles); the launch
+// has grid + n_omega workgroups.
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega,
-                         int n_omega, bool fp32, void* tiles, int* flags, uint32_t* ticket,
+                         int n_omega, bool fp32, void* tiles, int* flags, uint32_t* counters,
                          uint32_t* status, int grid, hipStream_t s);
 // Dynamic-LDS attributes of the factor / solve kernels for one tile and
 // precision; called when a handle is created, never on the launch path.
