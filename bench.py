@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--refine-iters", type=int, default=0)
+    ap.add_argument("--refine-tol", type=float, default=1e-8,
+                    help="mixed path: refinement tolerance of the projection and recovery solves "
+                         "(1e-8: the metric's own bound on the sigma_1 error; the library "
+                         "default 1e-10 costs one more correction per solve)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-shifts", type=int, default=1)
@@ -50,7 +54,8 @@ def parse():
     return ap.parse_args()
 
 
-def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, graph_reps):
+def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, graph_reps,
+             refine_tol=0.0):
     import torch
 
     import paper_1902_01458_amd as rr
@@ -58,7 +63,7 @@ def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, gr
     if autotune:
         tune = rr.autotune(prob, list(w.omegas), w.k, precision)
     f = rr.factor(prob, list(w.omegas), precision, k_max=w.k, tile=tune["tile"],
-                  grid=tune["grid"], refine_iters=refine_iters)
+                  grid=tune["grid"], refine_iters=refine_iters, refine_tol=refine_tol)
     f.check()
     stream = torch.cuda.current_stream()
     Q = f.empty_block(w.k)
@@ -201,7 +206,7 @@ def main():
     solve_bytes = n_om * (w.n * (2 * b + 1) * 16 + 2 * w.k * w.n * 16)
     auto = not args.no_autotune
     mixed = run_path(prob, w, "mixed", args.steps, args.warmup, args.tile, args.refine_iters,
-                     auto, args.graph_reps)
+                     auto, args.graph_reps, args.refine_tol)
     print(f"# mixed: {mixed['ms_per_step']:.1f} ms/step {mixed['calls_ms']}, refine "
           f"{mixed['refine']}, tune {mixed['tune']}", file=sys.stderr, flush=True)
     fp64 = None
@@ -222,7 +227,7 @@ def main():
                                f"half-bandwidth {b}, {n_om} shifts 0.25..8, k={w.k}, q={w.q}, "
                                "Phi-weighted Gaussian sketch, seed 0",
                    "tile": mixed["tune"]["tile"], "grid": mixed["tune"]["grid"],
-                   "autotuned": auto},
+                   "autotuned": auto, "refine_tol": args.refine_tol, "refine_tol_sketch": 1e-8},
         "gains_per_s": value * w.k,
         "sigma1_rel_err_vs_oracle": accuracy(mixed, gold),
         "refine_corrections": mixed["refine"],

@@ -251,11 +251,14 @@ __device__ void lu_blockinv(cplx<R>* S, int LD, uint32_t* status) {
         for (int i = 0; i < P; i++) at(c0 + i, c0 + P + t) = x[i];
       }
     } else if (uinv) {
+      // the 16 reciprocals of the diagonal at once (lane j: 1 / U_jj), so
+      // that no division sits on the substitution's dependency chain
+      const cplx<R> dinv = cinv(at(c0 + lane, c0 + lane));
 #pragma unroll
       for (int i = 0; i < P; i++) x[i] = cplx<R>{i == lane ? (R)1 : (R)0, (R)0};
 #pragma unroll
       for (int j = P - 1; j >= 0; j--) {
-        x[j] = cmul(x[j], cinv(at(c0 + j, c0 + j)));
+        x[j] = cmul(x[j], bcast(dinv, j));
 #pragma unroll
         for (int i = 0; i < j; i++) csub_mul(x[i], at(c0 + i, c0 + j), x[j]);
         __builtin_amdgcn_sched_barrier(0);
