@@ -283,6 +283,18 @@ rr_status rr_philox_raw(uint32_t* out_dev, int64_t count, uint32_t c1, uint32_t 
                         uint32_t k1, void* stream);
 rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, double* theta, void* stream);
 
+/* Test hook for the factorisation's task order (host only, no device call).
+ * Writes the ticket tasks of one shift of a band of B tiles each side and NB
+ * block rows, in the order the factor launch hands them out, as (kind, r, t)
+ * int32 triples into out[3*i .. 3*i+2] for i < cap (host memory): kind 0 =
+ * finalisation of tile (r, t) (its last update, then the triangular solve
+ * with the LU of diagonal tile min(r, t)), 1 = its early updates written as a
+ * partial tile, 2 / 3 = the chain tiles of diagonal tile r (column / row
+ * side).  Diagonal tiles are factored outside this order, one worker per
+ * shift.  Returns the number of tasks (which may exceed cap), or -1 if B or
+ * NB is not positive. */
+int64_t rr_factor_schedule(int32_t B, int32_t NB, int32_t* out, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif

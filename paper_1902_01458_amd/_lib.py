@@ -14,12 +14,12 @@ STATUS_NAMES = {0: "RR_OK", 1: "RR_ERR_INVALID", 2: "RR_ERR_SINGULAR", 3: "RR_ER
 RR_FP64, RR_MIXED = 0, 1
 RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
 
-# every symbol include/rr.h declares, plus the two test hooks of rr_operator.hip
+# every symbol include/rr.h declares (the last three are test hooks)
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
            "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_grad", "rr_check", "rr_refine_count",
            "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
-           "rr_sketch")
+           "rr_sketch", "rr_factor_schedule")
 
 
 class RRError(RuntimeError):
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
                           ctypes.c_uint32, vp],
         "rr_sketch": [pp, i32, u64, vp, vp],
         "rr_factor_bytes": [i32, i32, i32, i32, ctypes.c_int, i32],
+        "rr_factor_schedule": [i32, i32, vp, i64],
         "rr_set_allocator": [ALLOC_FN, FREE_FN, vp],
         "rr_graph_capture": [vp, i32, i32, u64, i32, ctypes.c_int, vp, vp, vp, vp, vp, vp,
                              ctypes.POINTER(vp)],
@@ -98,6 +99,7 @@ def lib() -> ctypes.CDLL:
     L.rr_factor_bytes.restype = ctypes.c_size_t
     L.rr_graph_free.restype = None
     L.rr_refine_count.restype = ctypes.c_int32
+    L.rr_factor_schedule.restype = ctypes.c_int64
     _lib = L
     return L
 

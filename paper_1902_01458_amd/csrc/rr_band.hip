@@ -468,7 +468,7 @@ struct Task {
 
 __host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B - 1 : 4; }
 
-__device__ __forceinline__ Task decode(int slot, int m, int B) {
+__host__ __device__ inline Task decode(int slot, int m, int B) {
   if (B < 2) {
     if (slot == 0) return {0, m + 1, m};
     if (slot == 1) return {0, m, m + 1};
@@ -490,9 +490,34 @@ __device__ __forceinline__ Task decode(int slot, int m, int B) {
 }
 
 // E(r, t) has work when its early range s in [mx-B, m-2] is non-empty.
-__device__ __forceinline__ bool has_early(int r, int t, int B) {
+__host__ __device__ inline bool has_early(int r, int t, int B) {
   int m = min(r, t), d = abs(r - t);
   return m >= 2 && d <= B - 2;
+}
+
+// Test hook (host only): the factor launch's ticket tasks of one shift, in
+// ticket order, as (kind, r, t) triples with the decoder above; tasks that
+// fall outside the matrix or have no work are skipped, as the kernel skips
+// them.  Writes at most `cap` triples and returns the count (or -1 if B or
+// NB is not positive).
+extern "C" int64_t rr_factor_schedule(int32_t B, int32_t NB, int32_t* out, int64_t cap) {
+  if (B <= 0 || NB <= 0) return -1;
+  const int slots = factor_slots(B);
+  int64_t n = 0;
+  for (int m = 0; m < NB; m++)
+    for (int slot = 0; slot < slots; slot++) {
+      const Task tk = decode(slot, m, B);
+      if (tk.r < 0 || tk.r >= NB || tk.t >= NB) continue;
+      if (tk.kind == 1 && !has_early(tk.r, tk.t, B)) continue;
+      if (tk.kind >= 2 && tk.r == 0) continue;
+      if (n < cap) {
+        out[3 * n] = tk.kind;
+        out[3 * n + 1] = tk.r;
+        out[3 * n + 2] = tk.t;
+      }
+      n++;
+    }
+  return n;
 }
 
 template <typename R, int T>
