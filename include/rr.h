@@ -24,6 +24,7 @@
  *   rr_gains         step 5 (SVD of B), eq. 8 (Halko response modes Q Ut) and
  *                    steps 6-9 (eq. 9: H v_j = sigma_j u_j, the paper's
  *                    recovery of sigma_j and u_j)
+ *   rr_resvd         optional steps 10-11: SVD of U^Sigma, improved V
  *   rr_grad          d sigma_1 / d(U, nu, omega) by first-order perturbation
  *                    of eq. 5 (not in the paper; see rr_grad below)
  *
@@ -195,6 +196,19 @@ rr_status rr_solve(rr_factors* f, int32_t k, const double* Bm, double* X, void* 
 rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z,
                    rr_response mode, double* sigma_B, double* sigma_AV, double* V,
                    double* Uresp, void* stream);
+
+/* Optional steps 10-11 of Algorithm 1: the SVD of U^Sigma = M^-1 V (the
+ * recovered, unnormalised response modes of step 6) gives orthonormal
+ * response modes U and gains sigma, and its right singular vectors W refine
+ * the forcing modes, V <- V W.  U^Sigma is Us (device (n_omega, k, n)
+ * complex) when scale is NULL, else Us with column j of shift w multiplied
+ * by scale[w*k + j] (device, n_omega*k doubles), so that the unit modes and
+ * sigma_AV of rr_gains can be passed as they are.  V: device (n_omega, k, n),
+ * the forcing modes of rr_gains.  Outputs: sigma (device n_omega*k,
+ * descending), U and Vnew (device (n_omega, k, n)); they may not alias the
+ * inputs or each other.  Everything runs in FP64. */
+rr_status rr_resvd(rr_factors* f, int32_t k, const double* Us, const double* scale,
+                   const double* V, double* sigma, double* U, double* Vnew, void* stream);
 
 /* Gradient of the leading gain (not part of the paper's method): for a
  * simple sigma with H v = sigma u and u^H H = sigma v^H, a perturbation gives

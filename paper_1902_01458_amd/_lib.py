@@ -16,7 +16,7 @@ RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
 
 # every symbol include/rr.h declares (the last three are test hooks)
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
-           "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_grad", "rr_check", "rr_refine_count",
+           "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_resvd", "rr_grad", "rr_check", "rr_refine_count",
            "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
            "rr_sketch", "rr_factor_schedule")
@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
         "rr_adjoint_solve": [vp, i32, vp, vp, vp],
         "rr_solve": [vp, i32, vp, vp, vp],
         "rr_gains": [vp, i32, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp],
+        "rr_resvd": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rr_grad": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
         "rr_check": [vp, vp],
         "rr_refine_count": [vp],

@@ -204,6 +204,22 @@ class Factors:
                              ctypes.c_void_p(_stream(stream))))
         return {"sigma_B": sB, "sigma_AV": sAV, "V": V, "U": U}
 
+    def resvd(self, Us: torch.Tensor, V: torch.Tensor, scale: Optional[torch.Tensor] = None,
+              out: Optional[dict] = None, stream=None) -> dict:
+        """Optional steps 10-11 of Algorithm 1 (rr_resvd): the SVD of U^Sigma
+        (Us, or Us scaled per column by `scale`, e.g. the unit modes U and
+        sigma_AV of gains()) gives sigma_svd, orthonormal U_svd and the
+        refined forcing modes V_svd = V W."""
+        k = Us.shape[1]
+        o = out or {}
+        sig = o.get("sigma_svd", torch.empty((self.n_omega, k), dtype=torch.float64,
+                                             device="cuda"))
+        U = o.get("U_svd", self.empty_block(k))
+        Vn = o.get("V_svd", self.empty_block(k))
+        check(lib().rr_resvd(self.handle, k, _ptr(Us), _ptr(scale), _ptr(V), _ptr(sig), _ptr(U),
+                             _ptr(Vn), ctypes.c_void_p(_stream(stream))))
+        return {"sigma_svd": sig, "U_svd": U, "V_svd": Vn}
+
     def grad(self, sigma1: torch.Tensor, u1: torch.Tensor, v1: torch.Tensor, stride: int,
              stream=None):
         """(dU (n_omega, nx, ny), dnu (n_omega,), domega (n_omega,)) of sigma_1."""
@@ -345,12 +361,18 @@ def factor(prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 3
 
 def resolvent(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
               precision: str = "fp64", response: str = "av", factors: Optional[Factors] = None,
-              check_status: bool = True, **kw) -> dict:
-    """Algorithm 1 for every shift: returns sigma_B, sigma_AV, V, U, Q (GPU tensors)."""
+              check_status: bool = True, optional_svd: bool = False, **kw) -> dict:
+    """Algorithm 1 for every shift: returns sigma_B, sigma_AV, V, U, Q (GPU
+    tensors), and with optional_svd (response "av" only) the optional steps
+    10-11 as sigma_svd, U_svd, V_svd."""
+    if optional_svd and response != "av":
+        raise ValueError("the optional SVD refines the AV recovery (response='av')")
     f = factors if factors is not None else factor(prob, omegas, precision, k_max=k, **kw)
     Q = f.sketch_solve(k, seed, q)
     Z = f.adjoint_solve(Q)
     out = f.gains(Q, Z, response)
+    if optional_svd:
+        out.update(f.resvd(out["U"], out["V"], scale=out["sigma_AV"]))
     out["Q"] = Q
     out["factors"] = f
     if check_status:

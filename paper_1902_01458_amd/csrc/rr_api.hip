@@ -434,6 +434,25 @@ rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z, r
   return RR_OK;
 }
 
+rr_status rr_resvd(rr_factors* f, int32_t k, const double* Us, const double* scale,
+                   const double* V, double* sigma, double* U, double* Vnew, void* stream) {
+  rr_status st = check_k(f, k);
+  if (st != RR_OK) return st;
+  if (!Us || !V || !sigma || !U || !Vnew) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (U == Us || U == V || Vnew == Us || Vnew == V || U == Vnew)
+    return fail(RR_ERR_INVALID, "outputs may not alias inputs or each other");
+  hipStream_t s = (hipStream_t)stream;
+  const double* X = Us;
+  if (scale) {  // U^Sigma from the unit response modes and their gains
+    RR_HIP(launch_scale_cols(f->n, f->n_omega, k, Us, scale, f->work2, s));
+    X = f->work2;
+  }
+  // step 10: U^Sigma = Qz R, R^H = Ut S W^H, so U^Sigma = (Qz W) S Ut^H: the
+  // left singular vectors are Qz W and the right ones Ut; step 11: V <- V Ut
+  RR_HIP(launch_small_svd(f->n, f->n_omega, k, X, V, sigma, U, Vnew, f->small, st_word(f), s));
+  return RR_OK;
+}
+
 rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const double* v1,
                   int64_t vec_stride, double* dU, double* dnu, double* domega, void* stream) {
   if (!f) return fail(RR_ERR_INVALID, "NULL handle");

@@ -154,6 +154,9 @@ hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q,
 hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const double* Q,
                             double* sigma, double* V, double* Uqu, SmallWs& ws,
                             uint32_t* status, hipStream_t s);
+// U_j = scale_j W_j for every shift (W may alias U)
+hipError_t launch_scale_cols(int n, int n_omega, int k, const double* W, const double* scale,
+                             double* U, hipStream_t s);
 // sigma_j = ||W_j||, U_j = W_j / sigma_j  (W may alias U)
 hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, double* sigma,
                                 double* U, SmallWs& ws, uint32_t* status, hipStream_t s);

@@ -450,15 +450,24 @@ __global__ void k_colnorm_final(int k, int nchunk, const double* partial, double
   }
 }
 
-__global__ void k_scale_cols(int64_t n, int k, const double2* W, const double* sigma, double2* U) {
+// U_j = W_j / sigma_j (divide; 0 where sigma_j = 0) or W_j * sigma_j.
+__global__ void k_scale_cols(int64_t n, int k, const double2* W, const double* sigma, double2* U,
+                             int divide) {
   int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
   int j = blockIdx.y, w = blockIdx.z;
   if (r >= n) return;
   double s = sigma[(int64_t)w * k + j];
-  double inv = s > 0 ? 1.0 / s : 0.0;
+  double c = divide ? (s > 0 ? 1.0 / s : 0.0) : s;
   int64_t off = ((int64_t)w * k + j) * n + r;
   double2 v = W[off];
-  U[off] = make_double2(v.x * inv, v.y * inv);
+  U[off] = make_double2(v.x * c, v.y * c);
+}
+
+hipError_t launch_scale_cols(int n, int n_omega, int k, const double* W, const double* scale,
+                             double* U, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, k, n_omega), dim3(256), 0, s,
+                     (int64_t)n, k, (const double2*)W, scale, (double2*)U, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, double* sigma,
@@ -472,7 +481,7 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
   hipLaunchKernelGGL(k_colnorm_final, dim3(n_omega), dim3(64), 0, s, k, nc, part, sigma, status);
   if (U)
     hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, k, n_omega), dim3(256), 0, s,
-                       (int64_t)n, k, (const double2*)W, (const double*)sigma, (double2*)U);
+                       (int64_t)n, k, (const double2*)W, (const double*)sigma, (double2*)U, 1);
   return hipGetLastError();
 }
 
