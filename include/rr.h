@@ -10,8 +10,12 @@
  * Sign convention: the paper writes the resolvent as (-i omega I - L)^-1 for
  * an e^{-i omega t} transform; this library uses M(omega) = i omega I - L.
  * For real L and real omega the gains agree and the modes are conjugated.
- * A complex omega = omega_r + i beta gives the discounted resolvent of the
- * paper's Section 2.1.
+ * Complex shifts: the paper's discounted resolvent (Section 2.1) takes
+ * omega = omega_r + i beta in its convention, i.e. [-i omega_r I - (L - beta
+ * I)]^-1, the growth rates of L lowered by beta.  Here that operator is
+ * M = i omega_r I - (L - beta I), reached with omega = omega_r - i beta
+ * (omega_im = -beta); for real L its gains are the paper's and its modes the
+ * complex conjugates.
  *
  * Call sequence (Algorithm 1):
  *   rr_factor        one LU of M(omega) per shift, reused by every solve

@@ -103,8 +103,10 @@ def shifted(L: sp.spmatrix, omega: complex) -> sp.csr_matrix:
     Eq. (4) writes the resolvent as [-i omega I - L]^(-1) for the e^(-i omega t)
     convention; with e^(+i omega t) it is [i omega I - L]^(-1).  For real L and
     real omega the two are complex conjugates of each other: same gains, modes
-    conjugated.  This oracle and the library both use the + sign.  A complex
-    omega = omega_r + i beta gives the discounted resolvent of Section 2.1.
+    conjugated.  This oracle and the library both use the + sign.  The
+    discounted resolvent of Section 2.1 (complex frequency omega_r + i beta
+    there, the growth rates of L lowered by beta) is i omega_r I - (L - beta I)
+    here, i.e. omega = omega_r - i beta.
     """
     n = L.shape[0]
     return (sp.identity(n, dtype=np.complex128, format="csr") * (1j * omega)

@@ -110,12 +110,18 @@ class BurgersProblem:
 
 
 class Factors:
-    """One band LU per shift (M(omega) = i omega I - L), owned by the library."""
+    """One band LU per shift (M(omega) = i omega I - L), owned by the library.
+    With discount = beta > 0 the shifts become omega - i beta: the discounted
+    resolvent of Section 2.1, the growth rates of L lowered by beta (the
+    paper's complex frequency omega + i beta in its e^{-i omega t} convention).
+    `omegas` keeps the shifts as factored."""
 
     def __init__(self, prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32,
                  tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
-                 refine_tol_sketch: float = 0.0, stream=None):
-        om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
+                 refine_tol_sketch: float = 0.0, stream=None, discount: float = 0.0):
+        # discount beta: the paper's discounted resolvent (Section 2.1),
+        # M = i omega I - (L - beta I), i.e. the shift omega - i beta here
+        om = np.asarray(omegas, dtype=np.complex128).reshape(-1) - 1j * discount
         self.prob = prob
         self.omegas = om
         self.n_omega = om.size

@@ -52,6 +52,30 @@ def test_diagonal_operator_closed_form():
         assert dense.sin_angle(r.V[:, j:j + 1], e[:, None]) < 1e-10
 
 
+def test_discounted_unstable_diagonal_closed_form():
+    # Section 2.1: growing modes (Re lambda > 0) discounted by beta above the
+    # largest growth rate; here the shift omega - i beta, so M = (i omega +
+    # beta) I - L and the gains are 1 / |i omega + beta - lambda|
+    nx, ny = 8, 8
+    n = 2 * nx * ny
+    c = coef_zero(nx, ny)
+    lam = -1e5 * (1.0 + np.arange(n) / n)
+    lam[[3, 10, 17, 40]] = [0.3, 0.05, -0.2, -0.9]
+    c[..., 0] = lam[0::2].reshape(nx, ny)
+    c[..., 6] = lam[1::2].reshape(nx, ny)
+    L = op.assemble(c)
+    omega, beta = 0.8, 0.5
+    exact = np.sort(1.0 / np.abs(1j * omega + beta - lam))[::-1]
+    r = resolvent.randomized_resolvent(L, omega - 1j * beta, sketch.test_matrix(n, 6, None, 0),
+                                       q=1)
+    np.testing.assert_allclose(r.sigma_B[:4], exact[:4], rtol=1e-12)
+    np.testing.assert_allclose(r.sigma_AV[:4], exact[:4], rtol=1e-12)
+    # the growing mode lambda = 0.3 is the most amplified one after discounting
+    e = np.zeros(n)
+    e[3] = 1
+    assert dense.sin_angle(r.V[:, :1], e[:, None]) < 1e-10
+
+
 def test_rotation_blocks_closed_form():
     # per node [[a, -c], [c, a]] through the coupling coefficients: normal,
     # eigenvalues a +- i c, gains 1/sqrt(a^2 + (omega -+ c)^2)
