@@ -136,6 +136,18 @@ typedef struct {
                             value of 1 or more means no correction at all      */
 } rr_tuning;
 
+/* Test matrices Omega of Algorithm 1 step 1 (Section 2.2.2), each weighted by
+ * the problem's Phi (eq. 10) when it has one.  RR_TM_RADEMACHER: real +-1
+ * entries.  RR_TM_SPARSE: ultrasparse Rademacher, zeta entries +-1 per row in
+ * random columns, the rest 0.  RR_TM_ORTHONORMAL: the Gaussian matrix with
+ * its columns orthonormalised (Cholesky QR) before the weighting. */
+typedef enum {
+  RR_TM_GAUSSIAN = 0,
+  RR_TM_RADEMACHER = 1,
+  RR_TM_SPARSE = 2,
+  RR_TM_ORTHONORMAL = 3
+} rr_test_matrix;
+
 typedef struct rr_factors rr_factors;
 
 /* Fill coef (and phi) for the 2-D linearised viscous Burgers operator about
@@ -182,6 +194,12 @@ rr_status rr_refactor(rr_factors* f, void* stream);
  * has a real positive diagonal.  Q: device (n_omega, k, n) complex output. */
 rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power_iters,
                           double* Q, void* stream);
+
+/* Test matrix of the handle's later rr_sketch_solve calls and graph
+ * captures (the default is RR_TM_GAUSSIAN).  zeta: nonzeros per row for
+ * RR_TM_SPARSE (0: min(k, 8); values above k act as k), ignored otherwise.
+ * Host only: no device call. */
+rr_status rr_set_test_matrix(rr_factors* f, rr_test_matrix kind, int32_t zeta);
 
 /* Step 4: Z = M^-H Q for every shift (B = Z^H).  Q, Z: device (n_omega, k, n). */
 rr_status rr_adjoint_solve(rr_factors* f, int32_t k, const double* Q, double* Z, void* stream);
@@ -296,10 +314,13 @@ const char* rr_last_error(void);
  * rr_philox_raw: out_dev[4*i .. 4*i+3] = Philox4x32-10 output words of counter
  * (i, c1, c2, 0) under key (k0, k1), for i < count (device, 4*count words).
  * rr_sketch: the test matrix of rr_sketch_solve, Theta (k, n) complex
- * (device), row weights p->phi (NULL = unweighted); p->coef is not read. */
+ * (device), row weights p->phi (NULL = unweighted); p->coef is not read.
+ * kind: an elementwise kind (RR_TM_ORTHONORMAL needs a handle and is
+ * rejected); zeta as for rr_set_test_matrix. */
 rr_status rr_philox_raw(uint32_t* out_dev, int64_t count, uint32_t c1, uint32_t c2, uint32_t k0,
                         uint32_t k1, void* stream);
-rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, double* theta, void* stream);
+rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, rr_test_matrix kind,
+                    int32_t zeta, double* theta, void* stream);
 
 /* Test hook for the factorisation's task order (host only, no device call).
  * Writes the ticket tasks of one shift of a band of B tiles each side and NB

@@ -13,13 +13,14 @@ STATUS_NAMES = {0: "RR_OK", 1: "RR_ERR_INVALID", 2: "RR_ERR_SINGULAR", 3: "RR_ER
                 8: "RR_ERR_TIMEOUT"}
 RR_FP64, RR_MIXED = 0, 1
 RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
+TEST_MATRICES = {"gaussian": 0, "rademacher": 1, "sparse": 2, "orthonormal": 3}
 
 # every symbol include/rr.h declares (the last three are test hooks)
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
            "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_resvd", "rr_grad", "rr_check", "rr_refine_count",
            "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
-           "rr_sketch", "rr_factor_schedule")
+           "rr_sketch", "rr_factor_schedule", "rr_set_test_matrix")
 
 
 class RRError(RuntimeError):
@@ -79,7 +80,8 @@ def lib() -> ctypes.CDLL:
         "rr_last_error": [],
         "rr_philox_raw": [vp, i64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                           ctypes.c_uint32, vp],
-        "rr_sketch": [pp, i32, u64, vp, vp],
+        "rr_sketch": [pp, i32, u64, ctypes.c_int, i32, vp, vp],
+        "rr_set_test_matrix": [vp, ctypes.c_int, i32],
         "rr_factor_bytes": [i32, i32, i32, i32, ctypes.c_int, i32],
         "rr_factor_schedule": [i32, i32, vp, i64],
         "rr_set_allocator": [ALLOC_FN, FREE_FN, vp],

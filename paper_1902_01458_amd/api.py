@@ -118,7 +118,8 @@ class Factors:
 
     def __init__(self, prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32,
                  tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
-                 refine_tol_sketch: float = 0.0, stream=None, discount: float = 0.0):
+                 refine_tol_sketch: float = 0.0, stream=None, discount: float = 0.0,
+                 test_matrix: str = "gaussian", zeta: int = 0):
         # discount beta: the paper's discounted resolvent (Section 2.1),
         # M = i omega I - (L - beta I), i.e. the shift omega - i beta here
         om = np.asarray(omegas, dtype=np.complex128).reshape(-1) - 1j * discount
@@ -137,6 +138,14 @@ class Factors:
                               im.ctypes.data_as(ctypes.c_void_p), self.n_omega, k_max,
                               PRECISIONS[precision], ctypes.byref(tune),
                               ctypes.c_void_p(_stream(stream)), ctypes.byref(self._h)))
+        if test_matrix != "gaussian":
+            self.set_test_matrix(test_matrix, zeta)
+
+    def set_test_matrix(self, kind: str, zeta: int = 0):
+        """Test matrix of later sketches (Section 2.2.2): "gaussian",
+        "rademacher", "sparse" (zeta nonzeros per row, 0: min(k, 8)) or
+        "orthonormal"; each weighted by the problem's Phi (eq. 10) if set."""
+        check(lib().rr_set_test_matrix(self.handle, _lib.TEST_MATRICES[kind], zeta))
 
     # -- lifetime ----------------------------------------------------------
     def free(self):
@@ -394,9 +403,12 @@ def philox_raw(count: int, c1: int = 0, c2: int = 0, key=(0, 0)) -> torch.Tensor
     return (out.to(torch.int64) & 0xFFFFFFFF).reshape(count, 4)
 
 
-def sketch(prob: BurgersProblem, k: int, seed: int = 0) -> torch.Tensor:
-    """The test matrix Theta (k, n) the sketch step draws (eq. 10 weighting)."""
+def sketch(prob: BurgersProblem, k: int, seed: int = 0, kind: str = "gaussian",
+           zeta: int = 0) -> torch.Tensor:
+    """The test matrix Theta (k, n) the sketch step draws (eq. 10 weighting),
+    for the elementwise kinds ("gaussian", "rademacher", "sparse")."""
     out = torch.empty((k, prob.n), dtype=torch.complex128, device="cuda")
     ps = prob.c_struct()
-    check(lib().rr_sketch(ctypes.byref(ps), k, seed, _ptr(out), ctypes.c_void_p(_stream())))
+    check(lib().rr_sketch(ctypes.byref(ps), k, seed, _lib.TEST_MATRICES[kind], zeta, _ptr(out),
+                          ctypes.c_void_p(_stream())))
     return out

@@ -380,7 +380,14 @@ rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power
   hipStream_t s = (hipStream_t)stream;
   const int64_t blk = (int64_t)k * f->n;
   RR_HIP(launch_fill_u32(f->ctrl + 4, 0u, kMaxRefine, s));
-  RR_HIP(launch_sketch(opdesc(f), f->phi, k, seed, f->theta, s));                   // step 1
+  {                                                                                 // step 1
+    const int z = f->tm_zeta <= 0 ? std::min(k, 8) : std::min<int>(f->tm_zeta, k);
+    RR_HIP(launch_sketch(opdesc(f), f->phi, k, seed, f->tm_kind, z, f->theta, s));
+    if (f->tm_kind == RR_TM_ORTHONORMAL) {  // orthonormal columns, then eq. 10's weights
+      RR_HIP(launch_cholqr2(f->n, 1, k, f->theta, f->theta, f->small, st_word(f), s));
+      if (f->phi) RR_HIP(launch_weight_rows(f->n, k, f->phi, f->theta, s));
+    }
+  }
   const double ts = f->refine_tol_sketch;
   if ((st = solve_any(f, k, 0, f->theta, 0, Q, ts, s)) != RR_OK) return st;         // step 2
   RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));       // step 3
@@ -390,6 +397,17 @@ rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power
     if ((st = solve_any(f, k, 0, f->work1, blk, Q, ts, s)) != RR_OK) return st;
     RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));
   }
+  return RR_OK;
+}
+
+rr_status rr_set_test_matrix(rr_factors* f, rr_test_matrix kind, int32_t zeta) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  if (kind != RR_TM_GAUSSIAN && kind != RR_TM_RADEMACHER && kind != RR_TM_SPARSE &&
+      kind != RR_TM_ORTHONORMAL)
+    return fail(RR_ERR_INVALID, "unknown test matrix kind");
+  if (zeta < 0) return fail(RR_ERR_INVALID, "zeta must be >= 0");
+  f->tm_kind = kind;
+  f->tm_zeta = zeta;
   return RR_OK;
 }
 

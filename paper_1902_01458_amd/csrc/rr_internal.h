@@ -112,8 +112,13 @@ hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, dou
 hipError_t launch_apply(const OpDesc& op, const double* omega /*dev 2*n_omega*/, int n_omega,
                         int k, int adjoint, const double* X, const double* Bm, int64_t bstride,
                         double* Y, hipStream_t s, const uint32_t* skip = nullptr);
-hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed,
-                         double* Theta, hipStream_t s);
+// Theta (k, n) of step 1 for an elementwise kind (RR_TM_ORTHONORMAL: the
+// unweighted Gaussian matrix, to be orthonormalised and weighted by the
+// caller); zeta: nonzeros per row of RR_TM_SPARSE, already in [1, k].
+hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed, int kind,
+                         int zeta, double* Theta, hipStream_t s);
+// Theta[j][r] *= phi[r / 2]
+hipError_t launch_weight_rows(int64_t n, int k, const double* phi, double* Theta, hipStream_t s);
 
 // Band LU: tiles = n_omega * tiles_per_omega() tiles of T*T complex (R = float|double).
 // counters: two device words (task tickets, diagonal-worker roles); the launch
@@ -188,6 +193,8 @@ struct rr_factors {
   int refine_iters;
   double refine_tol;         // projection / recovery solves
   double refine_tol_sketch;  // sketch and subspace-iteration solves
+  rr_test_matrix tm_kind = RR_TM_GAUSSIAN;  // step 1's test matrix
+  int tm_zeta = 0;
   // private copies of the problem
   double* coef = nullptr;
   double* phi = nullptr;

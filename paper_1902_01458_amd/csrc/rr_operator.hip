@@ -160,33 +160,74 @@ __global__ void k_philox_raw(uint32_t* out, int64_t count, uint32_t c1, uint32_t
   out[4 * i + 0] = c[0]; out[4 * i + 1] = c[1]; out[4 * i + 2] = c[2]; out[4 * i + 3] = c[3];
 }
 
-// Theta[j][r] = phi[r/2] * sqrt(-ln u1) * exp(2 pi i u2), u1 = (m1+1) 2^-53,
-// u2 = m2 2^-53 from the top 53 bits of (x0:x1) and (x2:x3) at counter (r, j, 0, 0).
+// Test matrix entry (r, j), weighted by phi[r/2] when phi is given:
+//   Gaussian (and the orthonormal kind before its QR): sqrt(-ln u1) exp(2 pi i u2),
+//     u1 = (m1+1) 2^-53, u2 = m2 2^-53 from the top 53 bits of (x0:x1) and
+//     (x2:x3) at counter (r, j, 0, 0);
+//   Rademacher: +-1, the sign being the top bit of x0 at that counter;
+//   sparse sign: that +-1 if column j is among the zeta columns of row r with
+//     the smallest keys (x0 at counter (r, j', 1, 0)), ties to the lower
+//     column, else 0.
 __global__ void k_sketch(int64_t n, int k, const double* __restrict__ phi, uint32_t k0,
-                         uint32_t k1, double2* __restrict__ theta) {
+                         uint32_t k1, int kind, int zeta, double2* __restrict__ theta) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int j = blockIdx.y;
   if (r >= n) return;
   uint32_t c[4] = {(uint32_t)r, (uint32_t)j, 0u, 0u};
   philox4x32_10(c, k0, k1);
-  uint64_t m1 = ((((uint64_t)c[0]) << 32) | c[1]) >> 11;
-  uint64_t m2 = ((((uint64_t)c[2]) << 32) | c[3]) >> 11;
-  const double two_m53 = 1.1102230246251565404e-16;
-  double u1 = ((double)m1 + 1.0) * two_m53;
-  double u2 = (double)m2 * two_m53;
-  double rad = sqrt(-log(u1));
-  double sn, cs;
-  sincospi(2.0 * u2, &sn, &cs);
-  double w = phi ? phi[r >> 1] : 1.0;
-  theta[(int64_t)j * n + r] = make_double2(w * rad * cs, w * rad * sn);
+  double2 v;
+  if (kind == RR_TM_RADEMACHER || kind == RR_TM_SPARSE) {
+    bool keep = true;
+    if (kind == RR_TM_SPARSE) {
+      uint32_t kc[4] = {(uint32_t)r, (uint32_t)j, 1u, 0u};
+      philox4x32_10(kc, k0, k1);
+      const uint32_t key = kc[0];
+      int rank = 0;
+      for (int jj = 0; jj < k; jj++) {
+        if (jj == j) continue;
+        uint32_t oc[4] = {(uint32_t)r, (uint32_t)jj, 1u, 0u};
+        philox4x32_10(oc, k0, k1);
+        rank += (oc[0] < key) || (oc[0] == key && jj < j);
+      }
+      keep = rank < zeta;
+    }
+    v = make_double2(keep ? ((c[0] >> 31) ? -1.0 : 1.0) : 0.0, 0.0);
+  } else {
+    uint64_t m1 = ((((uint64_t)c[0]) << 32) | c[1]) >> 11;
+    uint64_t m2 = ((((uint64_t)c[2]) << 32) | c[3]) >> 11;
+    const double two_m53 = 1.1102230246251565404e-16;
+    double u1 = ((double)m1 + 1.0) * two_m53;
+    double u2 = (double)m2 * two_m53;
+    double rad = sqrt(-log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    v = make_double2(rad * cs, rad * sn);
+  }
+  double w = (phi && kind != RR_TM_ORTHONORMAL) ? phi[r >> 1] : 1.0;
+  theta[(int64_t)j * n + r] = make_double2(w * v.x, w * v.y);
 }
 
-hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed,
-                         double* Theta, hipStream_t s) {
+hipError_t launch_sketch(const OpDesc& op, const double* phi, int k, uint64_t seed, int kind,
+                         int zeta, double* Theta, hipStream_t s) {
   int64_t n = op.n;
   dim3 grid((unsigned)((n + 255) / 256), k);
   hipLaunchKernelGGL(k_sketch, grid, dim3(256), 0, s, n, k, phi, (uint32_t)(seed & 0xffffffffu),
-                     (uint32_t)(seed >> 32), (double2*)Theta);
+                     (uint32_t)(seed >> 32), kind, zeta, (double2*)Theta);
+  return hipGetLastError();
+}
+
+__global__ void k_weight_rows(int64_t n, const double* __restrict__ phi, double2* theta) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double w = phi[r >> 1];
+  double2* t = theta + (int64_t)blockIdx.y * n + r;
+  double2 v = *t;
+  *t = make_double2(w * v.x, w * v.y);
+}
+
+hipError_t launch_weight_rows(int64_t n, int k, const double* phi, double* Theta, hipStream_t s) {
+  dim3 grid((unsigned)((n + 255) / 256), k);
+  hipLaunchKernelGGL(k_weight_rows, grid, dim3(256), 0, s, n, phi, (double2*)Theta);
   return hipGetLastError();
 }
 
@@ -204,11 +245,15 @@ extern "C" rr_status rr_philox_raw(uint32_t* out_dev, int64_t count, uint32_t c1
 }
 
 // Unweighted/weighted sketch written to a caller buffer (tests): Theta (k, n).
-extern "C" rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, double* theta,
-                               void* stream) {
+extern "C" rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, rr_test_matrix kind,
+                               int32_t zeta, double* theta, void* stream) {
   if (!p || !theta || k < 1 || p->nx < 1 || p->ny < 1) return RR_ERR_INVALID;
+  if (kind != RR_TM_GAUSSIAN && kind != RR_TM_RADEMACHER && kind != RR_TM_SPARSE)
+    return RR_ERR_INVALID;
+  const int z = zeta <= 0 ? (k < 8 ? k : 8) : (zeta < k ? zeta : k);
   rr::OpDesc op{p->nx, p->ny, 2 * p->nx * p->ny, p->coef};
-  return rr::launch_sketch(op, p->phi, k, seed, theta, (hipStream_t)stream) == hipSuccess
+  return rr::launch_sketch(op, p->phi, k, seed, kind, z, theta, (hipStream_t)stream) ==
+                 hipSuccess
              ? RR_OK
              : RR_ERR_HIP;
 }

@@ -58,6 +58,8 @@ def test_invalid_arguments_rejected_on_host():
     assert L.rr_adjoint_solve(None, 4, None, None, None) == 1
     assert L.rr_gains(None, 4, None, None, 0, None, None, None, None, None) == 1
     assert L.rr_resvd(None, 4, None, None, None, None, None, None, None) == 1
+    assert L.rr_set_test_matrix(None, 0, 0) == 1
+    assert L.rr_sketch(None, 4, 0, 0, 0, None, None) == 1
     assert L.rr_grad(None, None, None, None, 0, None, None, None, None) == 1
     assert L.rr_check(None, None) == 1
     assert L.rr_refine_count(None) == 0

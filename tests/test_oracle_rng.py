@@ -69,3 +69,44 @@ def test_gradient_weight_linear_flow():
     np.testing.assert_allclose(phi, 1.1, rtol=1e-14)
     Om = sketch.test_matrix(2 * nx * ny, 3, phi.ravel(), seed=0)
     np.testing.assert_allclose(Om, 1.1 * sketch.complex_normal(2 * nx * ny, 3), rtol=1e-15)
+
+
+def test_rademacher_signs_balanced_and_nested():
+    W = sketch.rademacher(20000, 8, seed=5)
+    assert set(np.unique(W)) == {-1.0, 1.0}
+    assert abs(W.mean()) < 0.02
+    # the sign is the top bit of word x0 of the Gaussian's counter: columns nest
+    np.testing.assert_array_equal(sketch.rademacher(20000, 3, seed=5), W[:, :3])
+    # and the signs of neighbouring columns are uncorrelated
+    assert abs(np.mean(W[:, 0] * W[:, 1])) < 0.03
+
+
+def test_sparse_sign_structure():
+    n, k = 4000, 10
+    for zeta, z in ((3, 3), (0, 8), (25, 10)):
+        S = sketch.sparse_sign(n, k, zeta, seed=2)
+        nz = S != 0
+        assert np.all(nz.sum(axis=1) == z)
+        # nonzeros carry the Rademacher signs of the same entries
+        R = sketch.rademacher(n, k, seed=2)
+        np.testing.assert_array_equal(S[nz], R[nz])
+    # every column is chosen about equally often (zeta / k of the rows)
+    S = sketch.sparse_sign(n, k, 3, seed=2)
+    frac = (S != 0).mean(axis=0)
+    assert np.all(np.abs(frac - 0.3) < 0.04)
+
+
+def test_orthonormal_test_matrix():
+    n, k = 500, 7
+    W = sketch.test_matrix(n, k, None, seed=4, kind="orthonormal")
+    np.testing.assert_allclose(W.conj().T @ W, np.eye(k), atol=1e-13)
+    G = sketch.complex_normal(n, k, seed=4)
+    # same column space as the Gaussian matrix, and W^H G upper triangular
+    # with a positive real diagonal (the R of G = W R)
+    R = W.conj().T @ G
+    np.testing.assert_allclose(np.tril(R, -1), 0, atol=1e-12)
+    assert np.all(np.abs(np.diag(R).imag) < 1e-12) and np.all(np.diag(R).real > 0)
+    # eq. 10's weights apply after the orthonormalisation
+    phi = np.linspace(0.5, 2.0, n // 2)
+    Wp = sketch.test_matrix(n, k, phi, seed=4, kind="orthonormal")
+    np.testing.assert_allclose(Wp, np.repeat(phi, 2)[:, None] * W, rtol=1e-15)
