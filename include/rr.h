@@ -134,7 +134,20 @@ typedef struct {
                             subspace-iteration solves, which only fix the
                             basis Q (default 1e-8).  For either tolerance a
                             value of 1 or more means no correction at all      */
+  int32_t refine_method; /* mixed only: RR_REFINE_PLAIN (default; correction
+                            d = M32^-1 r) or RR_REFINE_GMRES (GMRES-IR: d from
+                            gmres_restart steps of GMRES on M32^-1 M d =
+                            M32^-1 r with M applied in FP64, for shifts where
+                            kappa(M) eps_32 is near or above one and plain
+                            refinement stalls; Carson & Higham, SISC 2017).
+                            Each GMRES-IR correction costs gmres_restart + 1
+                            FP32 solves and holds gmres_restart + 2 more
+                            blocks of n_omega*k_max*n complex FP64 (not
+                            counted by rr_factor_bytes)                        */
+  int32_t gmres_restart; /* steps per GMRES-IR correction, 1 .. 16 (default 8) */
 } rr_tuning;
+
+enum { RR_REFINE_PLAIN = 0, RR_REFINE_GMRES = 1 };
 
 /* Test matrices Omega of Algorithm 1 step 1 (Section 2.2.2), each weighted by
  * the problem's Phi (eq. 10) when it has one.  RR_TM_RADEMACHER: real +-1

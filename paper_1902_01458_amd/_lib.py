@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "RR_OK", 1: "RR_ERR_INVALID", 2: "RR_ERR_SINGULAR", 3: "RR_ER
 RR_FP64, RR_MIXED = 0, 1
 RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
 TEST_MATRICES = {"gaussian": 0, "rademacher": 1, "sparse": 2, "orthonormal": 3}
+REFINE_METHODS = {"plain": 0, "gmres": 1}
 
 # every symbol include/rr.h declares (the last three are test hooks)
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
@@ -43,7 +44,8 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double),
-                ("refine_tol_sketch", ctypes.c_double)]
+                ("refine_tol_sketch", ctypes.c_double), ("refine_method", ctypes.c_int32),
+                ("gmres_restart", ctypes.c_int32)]
 
 
 _lib = None

@@ -119,7 +119,8 @@ class Factors:
     def __init__(self, prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32,
                  tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
                  refine_tol_sketch: float = 0.0, stream=None, discount: float = 0.0,
-                 test_matrix: str = "gaussian", zeta: int = 0):
+                 test_matrix: str = "gaussian", zeta: int = 0, refine_method: str = "plain",
+                 gmres_restart: int = 0):
         # discount beta: the paper's discounted resolvent (Section 2.1),
         # M = i omega I - (L - beta I), i.e. the shift omega - i beta here
         om = np.asarray(omegas, dtype=np.complex128).reshape(-1) - 1j * discount
@@ -132,7 +133,10 @@ class Factors:
         self._h = ctypes.c_void_p()
         re = np.ascontiguousarray(om.real)
         im = np.ascontiguousarray(om.imag)
-        tune = _lib.Tuning(tile, grid, refine_iters, refine_tol, refine_tol_sketch)
+        # refine_method "gmres": GMRES-IR corrections (mixed precision), for
+        # shifts where plain refinement with the FP32 LU stalls
+        tune = _lib.Tuning(tile, grid, refine_iters, refine_tol, refine_tol_sketch,
+                           _lib.REFINE_METHODS[refine_method], gmres_restart)
         ps = prob.c_struct()
         check(lib().rr_factor(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
                               im.ctypes.data_as(ctypes.c_void_p), self.n_omega, k_max,

@@ -74,7 +74,8 @@ rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
 void free_all(rr_factors* f) {
   void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->flags, f->ctrl, f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
-                f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->grad_partial};
+                f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->grad_partial,
+                f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial};
   for (void* p : ps) {
     if (!p) continue;
     if (f->dealloc) f->dealloc(p, f->alloc_ctx);
@@ -106,6 +107,39 @@ __global__ void k_latch_unless(const uint32_t* conv, uint32_t* status, uint32_t 
   if (threadIdx.x == 0 && !*conv) atomicOr(status, bit);
 }
 
+// GMRES-IR correction: r <- m steps of GMRES on M32^-1 M d = M32^-1 r (left
+// preconditioned, zero initial guess), every (shift, column) on its own
+// Krylov space, classical Gram-Schmidt applied twice.  Fixed launches; all of
+// them skip their work once every column has converged.
+hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStream_t s) {
+  GmresWs& g = f->gm;
+  const int m = g.m, n_omega = f->n_omega;
+  const int64_t blk = (int64_t)k * f->n, vstride = (int64_t)n_omega * blk;
+  const uint32_t* skip = conv_word(f);
+  auto V = [&](int i) { return g.V + 2 * i * vstride; };
+  hipError_t e = launch_fill_u32((uint32_t*)g.H, 0u, (int64_t)n_omega * k * (m + 1) * m * 4, s);
+  auto solve32 = [&](const double* in, double* out) {
+    return launch_solve(f->geom, f->n, n_omega, k, true, f->tiles, adjoint, in, blk, out, f->xs,
+                        f->flags, ticket_word(f), st_word(f), f->solve_grid, s, skip);
+  };
+  if (e == hipSuccess) e = solve32(r, V(0));
+  if (e == hipSuccess)
+    e = launch_colnorm_scale(f->n, n_omega, k, V(0), g.beta, V(0), f->small, st_word(f), s);
+  for (int j = 0; e == hipSuccess && j < m; j++) {
+    e = launch_apply(opdesc(f), f->omega, n_omega, k, adjoint, V(j), nullptr, blk, g.t, s, skip);
+    if (e == hipSuccess) e = solve32(g.t, V(j + 1));
+    for (int pass = 0; e == hipSuccess && pass < 2; pass++)
+      e = launch_gs_project(f->n, n_omega, k, j, g, V(j + 1), skip, s);
+    double* nrm = g.h;  // free until the next projection
+    if (e == hipSuccess)
+      e = launch_colnorm_scale(f->n, n_omega, k, V(j + 1), nrm, V(j + 1), f->small, st_word(f),
+                               s);
+    if (e == hipSuccess) e = launch_store_subdiag(n_omega, k, j, g, nrm, skip, s);
+  }
+  if (e == hipSuccess) e = launch_gmres_finish(f->n, n_omega, k, g, r, skip, s);
+  return e;
+}
+
 // X = M^-1 Bm (or M^-H): one FP64 band solve, or FP32 solves with FP64
 // residual refinement to `tol`.  Bm's blocks are bstride apart (0 = shared by
 // all shifts).  The mixed loop has a fixed number of launches; once every
@@ -119,12 +153,17 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
   double* res = f->work3;
   RR_HIP(launch_fill_u32(conv_word(f), 0u, 1, s));
   for (int it = 0; it < f->refine_iters; it++) {
-    // res = Bm - M X in FP64 from the stencil, then res <- M32^-1 res, X += res
+    // res = Bm - M X in FP64 from the stencil, then res <- M32^-1 res (or the
+    // GMRES-IR correction), X += res
     RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, k, adjoint, X, Bm, bstride, res, s,
                         conv_word(f)));
-    RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
-                        (int64_t)k * f->n, res, f->xs, f->flags, ticket_word(f), st_word(f),
-                        f->solve_grid, s, conv_word(f)));
+    if (f->gm.m > 0) {
+      RR_HIP(gmres_correction(f, k, adjoint, res, s));
+    } else {
+      RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
+                          (int64_t)k * f->n, res, f->xs, f->flags, ticket_word(f), st_word(f),
+                          f->solve_grid, s, conv_word(f)));
+    }
     RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
     RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, it, f->small, st_word(f),
                                 fail_word(f), s, conv_word(f)));
@@ -247,6 +286,11 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   if (T != 32 && T != 64) return fail(RR_ERR_INVALID, "tile must be 32 or 64");
   if (tune && (tune->refine_iters < 0 || tune->refine_iters > kMaxRefine))
     return fail(RR_ERR_INVALID, "refine_iters out of range");
+  if (tune && tune->refine_method != RR_REFINE_PLAIN && tune->refine_method != RR_REFINE_GMRES)
+    return fail(RR_ERR_INVALID, "unknown refine_method");
+  if (tune && tune->refine_method == RR_REFINE_GMRES &&
+      (tune->gmres_restart < 0 || tune->gmres_restart > kGmresMaxRestart))
+    return fail(RR_ERR_INVALID, "gmres_restart out of range");
   if (!is_dev_ptr(p->coef) || (p->phi && !is_dev_ptr(p->phi)) || (p->U && !is_dev_ptr(p->U)))
     return fail(RR_ERR_INVALID, "coef/phi/U must be device pointers");
 
@@ -310,6 +354,18 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->small.kmax = k_max;
   f->grad_nchunk = pl.grad_nchunk;
   ALLOC(f->grad_partial, pl.grad);
+  if (prec == RR_MIXED && tune && tune->refine_method == RR_REFINE_GMRES) {
+    const int m = tune->gmres_restart ? tune->gmres_restart : 8;
+    const size_t cols = (size_t)n_omega * k_max, cplx = 2 * sizeof(double);
+    f->gm.m = m;
+    ALLOC(f->gm.V, (size_t)(m + 1) * pl.vec);
+    ALLOC(f->gm.t, pl.vec);
+    ALLOC(f->gm.H, cols * (m + 1) * m * cplx);
+    ALLOC(f->gm.h, cols * (m + 1) * cplx);
+    ALLOC(f->gm.beta, cols * sizeof(double));
+    ALLOC(f->gm.y, cols * m * cplx);
+    ALLOC(f->gm.partial, cols * gmres_nchunk(n64) * (m + 1) * cplx);
+  }
 #undef ALLOC
   {
     hipError_t e = hipMemcpyAsync(f->coef, p->coef, nn * 12 * sizeof(double),
@@ -323,6 +379,10 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
       e = hipMemcpyAsync(f->omega, f->omega_host.data(), 2 * n_omega * sizeof(double),
                          hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_fill_u32(f->ctrl, 0u, 64, s);
+    // the Krylov blocks start finite (their norms are taken on every cycle,
+    // also the ones that skip their other work)
+    if (e == hipSuccess && f->gm.V)
+      e = launch_fill_u32((uint32_t*)f->gm.V, 0u, (int64_t)((f->gm.m + 1) * pl.vec / 4), s);
     if (e != hipSuccess) {
       st = fail(RR_ERR_HIP, hipGetErrorString(e));
       goto fail_free;

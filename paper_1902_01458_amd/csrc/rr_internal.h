@@ -165,6 +165,31 @@ hipError_t launch_scale_cols(int n, int n_omega, int k, const double* W, const d
 // sigma_j = ||W_j||, U_j = W_j / sigma_j  (W may alias U)
 hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, double* sigma,
                                 double* U, SmallWs& ws, uint32_t* status, hipStream_t s);
+// GMRES-IR workspace (rr_gmres.hip): m + 1 Krylov blocks V of n_omega*k_max*n
+// complex, the product block t, and per column (w*k + c) the Hessenberg
+// matrix H ((m+1) x m), the projections h (m+1), beta, y (m) and the chunk
+// partial sums of the projections.
+constexpr int kGmresMaxRestart = 16;
+struct GmresWs {
+  double* V = nullptr;
+  double* t = nullptr;
+  double* H = nullptr;
+  double* h = nullptr;
+  double* beta = nullptr;
+  double* y = nullptr;
+  double* partial = nullptr;
+  int m = 0;  // restart length; 0: plain refinement
+};
+int gmres_nchunk(int64_t n);
+// x -= V_{0..j} (V_{0..j}^H x) per column, the projections added to column j of H
+hipError_t launch_gs_project(int64_t n, int n_omega, int k, int j, const GmresWs& g, double* x,
+                             const uint32_t* skip, hipStream_t s);
+// H[j+1][j] = norm per column
+hipError_t launch_store_subdiag(int n_omega, int k, int j, const GmresWs& g, const double* norm,
+                                const uint32_t* skip, hipStream_t s);
+// y = argmin || beta e_1 - H y || per column, out = V_{0..m-1} y
+hipError_t launch_gmres_finish(int64_t n, int n_omega, int k, const GmresWs& g, double* out,
+                               const uint32_t* skip, hipStream_t s);
 // X += D after correction `it` (0-based) and the per-column convergence test
 // on e_j = ||D_j|| / ||X_j||: converged when e_j <= tol or when the error left,
 // estimated as e_j times the contraction (e_j itself after the first
@@ -193,6 +218,7 @@ struct rr_factors {
   int refine_iters;
   double refine_tol;         // projection / recovery solves
   double refine_tol_sketch;  // sketch and subspace-iteration solves
+  rr::GmresWs gm;                           // GMRES-IR (mixed only; gm.m = 0: plain)
   rr_test_matrix tm_kind = RR_TM_GAUSSIAN;  // step 1's test matrix
   int tm_zeta = 0;
   // private copies of the problem

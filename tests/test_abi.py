@@ -51,6 +51,11 @@ def test_invalid_arguments_rejected_on_host():
     bad_tile = _lib.Tuning(48, 0, 0, 0.0)
     assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 0, ctypes.byref(bad_tile), None,
                        ctypes.byref(h)) == 1
+    for bad in (_lib.Tuning(64, 0, 0, 0.0, 0.0, 2, 0), _lib.Tuning(64, 0, 0, 0.0, 0.0, 1, 17),
+                _lib.Tuning(64, 0, 0, 0.0, 0.0, 1, -1)):
+        assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 1, ctypes.byref(bad), None,
+                           ctypes.byref(h)) == 1
+        assert b"refine_method" in L.rr_last_error() or b"gmres_restart" in L.rr_last_error()
     assert not h
     assert L.rr_factor(ctypes.byref(p), one, None, 1, 4, 0, None, None, None) == 1
     # calls on a NULL handle
