@@ -456,14 +456,10 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
 //
 // Task decoding: slot -> (kind, r, t) for block step m.  Kinds: 0 = F,
 // 1 = E, 2 / 3 = the chain tiles of diagonal tile m (column / row side).
-//   slots 0 .. 2B-5: E of the off-diagonal tiles finalised at step m+1
-//     (distance 1 .. B-2)
-//   slots 2B-4, 2B-3: F(m+1, m), F(m, m+1)
-//   slots 2B-2, 2B-1: F(m+2, m), F(m, m+2)
-//   slot 2B: E(m+2, m+2), the early updates of the diagonal tile two steps
-//     on, right after its last inputs: its updates take most of a block step
-//     in one workgroup, and the diagonal worker waits for them
-//   slots 2B+1 .. 4B-4: F at distance 3 .. B
+//   slots 0 .. 2B-4: E of the tiles finalised at step m+1 (distance <= B-2),
+//     E(m+1, m+1) first (it feeds the next diagonal tile)
+//   slots 2B-3, 2B-2: F(m+1, m), F(m, m+1)
+//   slots 2B-1 .. 4B-4: F at distance 2 .. B
 //   slots 4B-3, 4B-2: the chain tiles of diagonal tile m
 // (B = 1: F(m+1, m), F(m, m+1) and the two chain tasks.)
 struct Task {
@@ -478,17 +474,16 @@ __host__ __device__ inline Task decode(int slot, int m, int B) {
     if (slot == 1) return {0, m, m + 1};
     return {slot == 2 ? 2 : 3, m, m};
   }
-  if (slot < 2 * B - 4) {
-    const int mm = m + 1, d = 1 + (slot >> 1);
-    return (slot & 1) ? Task{1, mm, mm + d} : Task{1, mm + d, mm};
+  if (slot < 2 * B - 3) {
+    const int mm = m + 1;
+    if (slot == 0) return {1, mm, mm};
+    const int d = (slot + 1) >> 1;
+    return (slot & 1) ? Task{1, mm + d, mm} : Task{1, mm, mm + d};
   }
-  if (slot == 2 * B - 4) return {0, m + 1, m};
-  if (slot == 2 * B - 3) return {0, m, m + 1};
-  if (slot == 2 * B - 2) return {0, m + 2, m};
-  if (slot == 2 * B - 1) return {0, m, m + 2};
-  if (slot == 2 * B) return {1, m + 2, m + 2};
+  if (slot == 2 * B - 3) return {0, m + 1, m};
+  if (slot == 2 * B - 2) return {0, m, m + 1};
   if (slot < 4 * B - 3) {
-    const int f = slot - (2 * B + 1), d = 3 + (f >> 1);
+    const int f = slot - (2 * B - 1), d = 2 + (f >> 1);
     return (f & 1) ? Task{0, m, m + d} : Task{0, m + d, m};
   }
   return {slot == 4 * B - 3 ? 2 : 3, m, m};
