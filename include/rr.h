@@ -201,7 +201,8 @@ rr_status rr_refactor(rr_factors* f, void* stream);
 /* Steps 1-3 of Algorithm 1 with q rounds of subspace iteration (Section
  * 2.2.1): Theta[r, j] = phi[r/2] * w(r, j) with w a standard complex normal
  * drawn by Box-Muller from Philox4x32-10 at counter (r, j, 0, 0) under key
- * (seed & 0xffffffff, seed >> 32); one Theta shared by every shift.  Then
+ * (seed & 0xffffffff, seed >> 32), or another test matrix chosen with
+ * rr_set_test_matrix; one Theta shared by every shift.  Then
  * Y = M^-1 Theta, Q = orth(Y); q times: Q = orth(M^-1 orth(M^-H Q)).
  * orth() is Cholesky QR applied twice (Gram and Cholesky in FP64), whose R
  * has a real positive diagonal.  Q: device (n_omega, k, n) complex output. */
@@ -211,7 +212,8 @@ rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power
 /* Test matrix of the handle's later rr_sketch_solve calls and graph
  * captures (the default is RR_TM_GAUSSIAN).  zeta: nonzeros per row for
  * RR_TM_SPARSE (0: min(k, 8); values above k act as k), ignored otherwise.
- * Host only: no device call. */
+ * Host only: no device call.  RR_ERR_INVALID for a NULL handle, an unknown
+ * kind or a negative zeta (the setting is then unchanged). */
 rr_status rr_set_test_matrix(rr_factors* f, rr_test_matrix kind, int32_t zeta);
 
 /* Step 4: Z = M^-H Q for every shift (B = Z^H).  Q, Z: device (n_omega, k, n). */
@@ -241,7 +243,11 @@ rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z,
  * sigma_AV of rr_gains can be passed as they are.  V: device (n_omega, k, n),
  * the forcing modes of rr_gains.  Outputs: sigma (device n_omega*k,
  * descending), U and Vnew (device (n_omega, k, n)); they may not alias the
- * inputs or each other.  Everything runs in FP64. */
+ * inputs or each other.  Everything runs in FP64, on the handle's
+ * workspaces (no allocation).  RR_ERR_INVALID for a NULL handle or pointer,
+ * k outside [1, k_max] or aliased outputs, before anything is launched;
+ * device-side failures (a non-finite Gram matrix) are latched as for the
+ * other calls (rr_check). */
 rr_status rr_resvd(rr_factors* f, int32_t k, const double* Us, const double* scale,
                    const double* V, double* sigma, double* U, double* Vnew, void* stream);
 
