@@ -85,3 +85,30 @@ def test_gmres_ir_pipeline_matches_oracle():
     assert gain_errors(to_np(out["sigma_B"])[0], ref.sigma_B).max() <= 1e-8
     assert gain_errors(to_np(out["sigma_AV"])[0], ref.sigma_AV).max() <= 1e-8
     out["factors"].free()
+
+
+def test_gmres_ir_graph_replays_equal_eager_pass():
+    """A captured pass with GMRES-IR corrections (fills and kernels only)
+    replays bit for bit what the eager calls compute, with unrelated eager
+    work and synchronisations between the replays."""
+    w = W.small("gg", 32, 24, nu=1e-2, omegas=(0.4, 1.7, 4.0), k=6, q=1)
+    prob = rr().BurgersProblem.from_workload(w)
+    f = rr().factor(prob, list(w.omegas), "mixed", k_max=w.k, tile=32, refine_method="gmres",
+                    gmres_restart=4)
+    Q = f.sketch_solve(w.k, w.seed, w.q)
+    Z = f.adjoint_solve(Q)
+    ref = f.gains(Q, Z, "av")
+    f.check()
+    ref = {key: to_np(v) for key, v in ref.items() if v is not None}
+    g = rr().capture(f, w.k, w.seed, w.q, "av", refactor=True)
+    X = torch.randn((len(w.omegas), 3, w.n), dtype=torch.complex128, device="cuda")
+    for rep in range(3):
+        Y = prob.apply(list(w.omegas), X)
+        torch.cuda.synchronize()
+        assert torch.isfinite(torch.view_as_real(Y)).all()
+        out = g.launch()
+        f.check()
+        for key in ("sigma_B", "sigma_AV", "V", "U"):
+            np.testing.assert_array_equal(to_np(out[key]), ref[key])
+    g.free()
+    f.free()
