@@ -93,3 +93,26 @@ def test_k_convergence_and_test_matrices_against_dense_svd():
     for name, es, eu in rows:
         print(f"{name:18s} " + "  ".join(f"{e:9.1e}" for e in es) + "   "
               + "  ".join(f"{e:7.1e}" for e in eu))
+
+
+@pytest.mark.parametrize("kind", ["sparse", "orthonormal"])
+def test_graph_replay_with_test_matrix_kind(kind):
+    """The handle's test matrix is part of a captured pass: the replays equal
+    the eager calls bit for bit (the orthonormal kind adds a CholQR2 of Theta)."""
+    import torch
+    w = W.small("gk", 24, 16, nu=1e-2, omegas=(0.5, 2.5), k=6, q=1)
+    prob = rr().BurgersProblem.from_workload(w)
+    f = rr().factor(prob, list(w.omegas), "fp64", k_max=w.k, tile=32, test_matrix=kind, zeta=2)
+    Q = f.sketch_solve(w.k, w.seed, w.q)
+    Z = f.adjoint_solve(Q)
+    ref = {key: to_np(v) for key, v in f.gains(Q, Z, "av").items() if v is not None}
+    f.check()
+    g = rr().capture(f, w.k, w.seed, w.q, "av", refactor=True)
+    for rep in range(3):
+        torch.cuda.synchronize()
+        out = g.launch()
+        f.check()
+        for key in ("sigma_B", "sigma_AV", "V", "U"):
+            np.testing.assert_array_equal(to_np(out[key]), ref[key])
+    g.free()
+    f.free()
