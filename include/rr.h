@@ -205,7 +205,11 @@ rr_status rr_refactor(rr_factors* f, void* stream);
  * rr_set_test_matrix; one Theta shared by every shift.  Then
  * Y = M^-1 Theta, Q = orth(Y); q times: Q = orth(M^-1 orth(M^-H Q)).
  * orth() is Cholesky QR applied twice (Gram and Cholesky in FP64), whose R
- * has a real positive diagonal.  Q: device (n_omega, k, n) complex output. */
+ * has a real positive diagonal; for a shift whose Gram matrix is not
+ * numerically positive definite (cond(Y) above about 1e8) it is shifted
+ * Cholesky QR3 (Fukaya et al., SISC 2020), and RR_ERR_BREAKDOWN is latched
+ * only if that fails too.  The same holds for the QR of Z in rr_gains and of
+ * U^Sigma in rr_resvd.  Q: device (n_omega, k, n) complex output. */
 rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power_iters,
                           double* Q, void* stream);
 

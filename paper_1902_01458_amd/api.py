@@ -17,10 +17,17 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check, lib
+from ._lib import RRError, check, lib
 
 PRECISIONS = {"fp64": _lib.RR_FP64, "mixed": _lib.RR_MIXED}
 RESPONSES = {"av": _lib.RR_RESP_AV, "qu": _lib.RR_RESP_QU, "none": _lib.RR_RESP_NONE}
+
+# numerical failures of a mixed-precision pass that an FP64 factorisation can
+# cure: a zero or non-finite FP32 pivot, refinement that missed its tolerance,
+# a CholeskyQR breakdown or non-finite values downstream of a stalled solve
+_FP64_CURABLE = (2, 3, 4, 5)
+# Factors() options that only the mixed path reads
+_MIXED_ONLY = ("refine_iters", "refine_tol", "refine_tol_sketch", "refine_method", "gmres_restart")
 
 
 def _stream(stream=None) -> int:
@@ -346,32 +353,60 @@ def autotune(prob: BurgersProblem, omegas, k: int, precision: str = "fp64",
     return {"tile": t.tile, "grid": t.grid, "ms": ms.value}
 
 
+def _sweep_chunk(prob, om, k, seed, q, precision, tile, grid):
+    f = factor(prob, om, precision, k_max=k, tile=tile, grid=grid)
+    g = None
+    try:
+        g = capture(f, k, seed, q, "av", refactor=False)
+        out = g.launch()
+        f.check()
+        return out["sigma_B"].clone(), out["sigma_AV"].clone()
+    finally:
+        if g is not None:
+            g.free()
+        f.free()
+
+
+def _chunk_size(prob, k, precision, tile, memory_fraction, n_omega):
+    free, _ = torch.cuda.mem_get_info()
+    per = factor_bytes(prob.nx, prob.ny, 1, k, precision, tile) + 6 * k * prob.n * 16
+    return max(1, min(n_omega, int(memory_fraction * free // per)))
+
+
 def sweep(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
           precision: str = "fp64", tune: Optional[dict] = None, chunk: int = 0,
-          memory_fraction: float = 0.8) -> dict:
+          memory_fraction: float = 0.8, on_failure: str = "raise") -> dict:
     """Frequency sweep sharing one L: the shifts are processed in chunks that
     fit in device memory (rr_factor_bytes), each chunk as one captured graph
     (factorisation, sketch, subspace iteration, adjoint solve, SVD, eq. 9).
-    Returns sigma_B, sigma_AV (n_omega, k) on the GPU and the chunk size."""
+    With on_failure="fp64", a mixed-precision chunk that reports a numerical
+    failure is refactored and run again in FP64 (in sub-chunks sized for the
+    FP64 factors). Returns sigma_B, sigma_AV (n_omega, k) on the GPU, the chunk
+    size and the first shift index of every chunk redone in FP64."""
+    if on_failure not in ("raise", "fp64"):
+        raise ValueError("on_failure must be 'raise' or 'fp64'")
     om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
     tile = int(tune["tile"]) if tune else 0
     grid = int(tune["grid"]) if tune else 0
     if chunk <= 0:
-        free, _ = torch.cuda.mem_get_info()
-        per = factor_bytes(prob.nx, prob.ny, 1, k, precision, tile) + 6 * k * prob.n * 16
-        chunk = max(1, min(om.size, int(memory_fraction * free // per)))
+        chunk = _chunk_size(prob, k, precision, tile, memory_fraction, om.size)
     sB = torch.empty((om.size, k), dtype=torch.float64, device="cuda")
     sAV = torch.empty((om.size, k), dtype=torch.float64, device="cuda")
+    redone = []
     for c0 in range(0, om.size, chunk):
-        f = factor(prob, om[c0:c0 + chunk], precision, k_max=k, tile=tile, grid=grid)
-        g = capture(f, k, seed, q, "av", refactor=False)
-        out = g.launch()
-        f.check()
-        sB[c0:c0 + chunk] = out["sigma_B"]
-        sAV[c0:c0 + chunk] = out["sigma_AV"]
-        g.free()
-        f.free()
-    return {"sigma_B": sB, "sigma_AV": sAV, "chunk": chunk}
+        c1 = min(om.size, c0 + chunk)
+        try:
+            sB[c0:c1], sAV[c0:c1] = _sweep_chunk(prob, om[c0:c1], k, seed, q, precision, tile,
+                                                 grid)
+        except RRError as e:
+            if on_failure != "fp64" or precision != "mixed" or e.status not in _FP64_CURABLE:
+                raise
+            sub = _chunk_size(prob, k, "fp64", 0, memory_fraction, c1 - c0)
+            for s0 in range(c0, c1, sub):
+                s1 = min(c1, s0 + sub)
+                sB[s0:s1], sAV[s0:s1] = _sweep_chunk(prob, om[s0:s1], k, seed, q, "fp64", 0, 0)
+            redone.append(c0)
+    return {"sigma_B": sB, "sigma_AV": sAV, "chunk": chunk, "fp64_chunks": redone}
 
 
 def factor(prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 32, **kw) -> Factors:
@@ -380,22 +415,46 @@ def factor(prob: BurgersProblem, omegas, precision: str = "fp64", k_max: int = 3
 
 def resolvent(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
               precision: str = "fp64", response: str = "av", factors: Optional[Factors] = None,
-              check_status: bool = True, optional_svd: bool = False, **kw) -> dict:
+              check_status: bool = True, optional_svd: bool = False, on_failure: str = "raise",
+              **kw) -> dict:
     """Algorithm 1 for every shift: returns sigma_B, sigma_AV, V, U, Q (GPU
     tensors), and with optional_svd (response "av" only) the optional steps
-    10-11 as sigma_svd, U_svd, V_svd."""
+    10-11 as sigma_svd, U_svd, V_svd. out["precision"] names the path that
+    produced the result.
+
+    on_failure="fp64" is the policy for a mixed-precision pass that fails
+    numerically (refinement not converged, a zero FP32 pivot, a CholeskyQR
+    breakdown or non-finite values): every shift is refactored in FP64 and the
+    pass runs again with the same sketch; out["fallback_status"] holds the
+    status of the failed pass. It needs the factors to be made here and the
+    status to be checked; on the FP64 path it changes nothing."""
     if optional_svd and response != "av":
         raise ValueError("the optional SVD refines the AV recovery (response='av')")
+    if on_failure not in ("raise", "fp64"):
+        raise ValueError("on_failure must be 'raise' or 'fp64'")
+    if on_failure == "fp64" and (factors is not None or not check_status):
+        raise ValueError("the FP64 fallback needs factors made here and check_status=True")
     f = factors if factors is not None else factor(prob, omegas, precision, k_max=k, **kw)
-    Q = f.sketch_solve(k, seed, q)
-    Z = f.adjoint_solve(Q)
-    out = f.gains(Q, Z, response)
-    if optional_svd:
-        out.update(f.resvd(out["U"], out["V"], scale=out["sigma_AV"]))
+    try:
+        Q = f.sketch_solve(k, seed, q)
+        Z = f.adjoint_solve(Q)
+        out = f.gains(Q, Z, response)
+        if optional_svd:
+            out.update(f.resvd(out["U"], out["V"], scale=out["sigma_AV"]))
+        if check_status:
+            f.check()
+    except RRError as e:
+        if on_failure != "fp64" or f.precision != "mixed" or e.status not in _FP64_CURABLE:
+            raise
+        f.free()
+        kw64 = {key: v for key, v in kw.items() if key not in _MIXED_ONLY}
+        out = resolvent(prob, omegas, k, q, seed, "fp64", response, None, True, optional_svd,
+                        **kw64)
+        out["fallback_status"] = e.status
+        return out
     out["Q"] = Q
     out["factors"] = f
-    if check_status:
-        f.check()
+    out["precision"] = f.precision
     return out
 
 

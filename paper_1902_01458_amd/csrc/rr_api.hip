@@ -74,7 +74,7 @@ rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
 void free_all(rr_factors* f) {
   void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->flags, f->ctrl, f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
-                f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->grad_partial,
+                f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->small.shifted, f->grad_partial,
                 f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial};
   for (void* p : ps) {
     if (!p) continue;
@@ -179,12 +179,13 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
 // Device allocations of a handle, in one place for rr_factor and rr_factor_bytes.
 struct Plan {
   BandGeom geom;
-  size_t coef, phi, U, omega, tiles, xs, flags, ctrl, theta, vec, work3, partial, kk2, rho, grad;
+  size_t coef, phi, U, omega, tiles, xs, flags, ctrl, theta, vec, work3, partial, kk2, rho, shifted,
+      grad;
   int nchunk, grad_nchunk;
   size_t nflags;
   size_t total() const {
     return coef + phi + U + omega + tiles + xs + flags + ctrl + theta + 2 * vec + work3 + partial +
-           5 * kk2 + rho + grad;
+           5 * kk2 + rho + shifted + grad;
   }
 };
 
@@ -214,6 +215,7 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   pl.partial = (size_t)n_omega * pl.nchunk * kk * 2 * sizeof(double);
   pl.kk2 = (size_t)n_omega * kk * 2 * sizeof(double);
   pl.rho = prec == RR_MIXED ? (size_t)n_omega * 64 * sizeof(double) : 0;
+  pl.shifted = (size_t)n_omega * sizeof(uint32_t);
   pl.grad_nchunk = (int)((nn + 255) / 256);
   pl.grad = (size_t)n_omega * pl.grad_nchunk * 2 * sizeof(double);
   return pl;
@@ -350,6 +352,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   ALLOC(f->small.W, pl.kk2);
   ALLOC(f->small.Ut, pl.kk2);
   if (prec == RR_MIXED) ALLOC(f->small.rho, pl.rho);
+  ALLOC(f->small.shifted, pl.shifted);
   f->small.nchunk = pl.nchunk;
   f->small.kmax = k_max;
   f->grad_nchunk = pl.grad_nchunk;

@@ -148,13 +148,16 @@ struct SmallWs {   // workspace for tall-skinny reductions
   double* W;           // n_omega * kmax*kmax complex (SVD right vectors)
   double* Ut;          // n_omega * kmax*kmax complex (SVD left vectors)
   double* rho;         // n_omega * 64: each column's last relative correction (refinement)
+  uint32_t* shifted;   // n_omega: 1 where the first Cholesky QR pass needed the shift
   int nchunk;
   int kmax;
 };
 // CholQR2: Q = Y R^-1 with R upper, real positive diagonal; Q may alias Y.
+// A shift whose Gram matrix is not numerically positive definite takes
+// shifted CholeskyQR3 instead (three passes, the first with a diagonal shift).
 hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q,
                           SmallWs& ws, uint32_t* status, hipStream_t s);
-// Z = Qz R (CholQR2); SVD of R^H = Ut S W^H; sigma = S; V = Z R^-1 W;
+// Z = Qz R (CholQR2, or shifted CholQR3 as above); SVD of R^H = Ut S W^H; sigma = S; V = Z R^-1 W;
 // if Uqu != NULL also Uqu = Q Ut.
 hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const double* Q,
                             double* sigma, double* V, double* Uqu, SmallWs& ws,

@@ -26,12 +26,15 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
 // t accumulates the 2 x 2 group of entries (2 t/16 .. +1, 2 (t%16) .. +1) on
 // and above the diagonal (the Cholesky reads the upper triangle only); the
 // sketch width is at most KM = 32, so 256 threads cover every group.
+// With only_if != NULL a shift whose only_if[w] is zero is skipped.
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const double2* __restrict__ Y,
                                                       const double2* __restrict__ Tm, int kmax,
-                                                      int nchunk, double2* __restrict__ partial) {
+                                                      int nchunk, double2* __restrict__ partial,
+                                                      const uint32_t* __restrict__ only_if) {
   __shared__ double2 ys[kSub][KM + 1];
   __shared__ double2 tm[KM][KM];
   const int w = blockIdx.y, chunk = blockIdx.x;
+  if (only_if && only_if[w] == 0) return;
   const double2* Yw = Y + (int64_t)w * k * n;
   if (Tm) {
     for (int idx = threadIdx.x; idx < k * k; idx += 256)
@@ -97,50 +100,77 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const do
 }
 
 // Sum the partials (fixed order), Cholesky G = R^H R (R upper, real positive
-// diagonal), Rinv = R^-1.  compose != 0: R <- Rnew Rold, Rinv <- Rinv_old Rinv_new.
-__global__ __launch_bounds__(256) void k_chol(int k, int kmax, int nchunk,
+// diagonal), Rinv = R^-1.  Passes 1 and 2 compose: R <- Rnew Rold,
+// Rinv <- Rinv_old Rinv_new.
+//
+// Cholesky QR breaks down once cond(Y) passes about u^-1/2 (1e8): the Gram
+// matrix is then not numerically positive definite.  Pass 0 then takes the
+// Cholesky factor of G + s I instead, with the shift of Fukaya, Kannan,
+// Nakatsukasa, Yamamoto & Yanagisawa (shifted CholeskyQR3, SISC 2020),
+// s = 11 (m k + k (k + 1)) u ||Y||_F^2 (m + 2 in place of m for complex inner
+// products; ||Y||_F^2 = trace G bounds ||Y||_2^2), and sets shifted[w]; Y R^-1
+// then has a condition number near (u m k)^-1/2, which the two passes that
+// follow make orthonormal.  Pass 2 runs only for shifts with shifted[w] set.
+// A breakdown that remains latches ST_BREAKDOWN (the pivot is replaced by 1).
+__global__ __launch_bounds__(256) void k_chol(int k, int kmax, int nchunk, int64_t m,
                                               const double2* __restrict__ partial,
                                               double2* __restrict__ Rg, double2* __restrict__ Rinvg,
-                                              int compose, uint32_t* status) {
+                                              int pass, uint32_t* __restrict__ shifted,
+                                              uint32_t* status) {
   __shared__ double2 G[KM][KM + 1];
   __shared__ double2 Rn[KM][KM + 1];
   __shared__ double2 Ri[KM][KM + 1];
   __shared__ int bad;
+  __shared__ double shift;
   const int w = blockIdx.x;
-  for (int pr = threadIdx.x; pr < k * k; pr += 256) {  // upper triangle (all that is used)
-    double2 s = make_double2(0, 0);
-    if (pr % k >= pr / k) {
-      for (int c = 0; c < nchunk; c++) {
-        double2 v = partial[((int64_t)w * nchunk + c) * kmax * kmax + pr];
-        s.x += v.x; s.y += v.y;
+  if (pass == 2 && shifted[w] == 0) return;
+  int attempt = 0;
+  for (;; attempt++) {
+    for (int pr = threadIdx.x; pr < k * k; pr += 256) {  // upper triangle (all that is used)
+      double2 s = make_double2(0, 0);
+      if (pr % k >= pr / k) {
+        for (int c = 0; c < nchunk; c++) {
+          double2 v = partial[((int64_t)w * nchunk + c) * kmax * kmax + pr];
+          s.x += v.x; s.y += v.y;
+        }
+        if (attempt && pr % k == pr / k) s.x += shift;
       }
+      G[pr / k][pr % k] = s;
     }
-    G[pr / k][pr % k] = s;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    if (attempt == 0 && threadIdx.x == 0) {
+      double tr = 0;
+      for (int j = 0; j < k; j++) tr += G[j][j].x;
+      shift = 11.0 * ((double)(m + 2) * k + (double)k * (k + 1)) * 0x1p-53 * tr;
+    }
+    // right-looking Cholesky on the upper triangle: G = R^H R
+    for (int j = 0; j < k; j++) {
+      if (threadIdx.x == 0) {
+        double d = G[j][j].x;
+        if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
+        G[j][j] = make_double2(sqrt(d), 0.0);
+      }
+      __syncthreads();
+      double rjj = G[j][j].x;
+      for (int c = j + 1 + threadIdx.x; c < k; c += 256) {
+        G[j][c].x /= rjj; G[j][c].y /= rjj;
+      }
+      __syncthreads();
+      int wd = k - 1 - j;
+      for (int idx = threadIdx.x; idx < wd * wd; idx += 256) {
+        int a = j + 1 + idx / wd, c = j + 1 + idx % wd;
+        if (c < a) continue;
+        double2 p = cmulc(G[j][a], G[j][c]);  // R[j][a]^* R[j][c]
+        G[a][c].x -= p.x; G[a][c].y -= p.y;
+      }
+      __syncthreads();
+    }
+    if (!(bad && pass == 0 && attempt == 0)) break;  // bad is block-uniform here
+    __syncthreads();
   }
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  // right-looking Cholesky on the upper triangle: G = R^H R
-  for (int j = 0; j < k; j++) {
-    if (threadIdx.x == 0) {
-      double d = G[j][j].x;
-      if (!(d > 0.0) || !isfinite(d)) { bad = 1; d = 1.0; }
-      G[j][j] = make_double2(sqrt(d), 0.0);
-    }
-    __syncthreads();
-    double rjj = G[j][j].x;
-    for (int c = j + 1 + threadIdx.x; c < k; c += 256) {
-      G[j][c].x /= rjj; G[j][c].y /= rjj;
-    }
-    __syncthreads();
-    int wd = k - 1 - j;
-    for (int idx = threadIdx.x; idx < wd * wd; idx += 256) {
-      int a = j + 1 + idx / wd, c = j + 1 + idx % wd;
-      if (c < a) continue;
-      double2 p = cmulc(G[j][a], G[j][c]);  // R[j][a]^* R[j][c]
-      G[a][c].x -= p.x; G[a][c].y -= p.y;
-    }
-    __syncthreads();
-  }
+  if (pass == 0 && threadIdx.x == 0) shifted[w] = attempt;
+  const int compose = pass > 0;
   for (int idx = threadIdx.x; idx < k * k; idx += 256) {
     int a = idx / k, c = idx % k;
     Rn[a][c] = c >= a ? G[a][c] : make_double2(0, 0);
@@ -227,20 +257,28 @@ __global__ __launch_bounds__(256) void k_apply_small(int64_t n, int k, const dou
 
 static int nchunks(int64_t n) { return (int)((n + kChunkRows - 1) / kChunkRows); }
 
+// Cholesky QR of Y (n_omega blocks of n x k) into ws.R and ws.Rinv: two
+// passes, and for shifts whose first Cholesky broke down a shifted first pass
+// and a third (shifted CholeskyQR3).  The launch sequence is the same either
+// way (the third pass returns at once for the other shifts).
+static void chol_passes(int n, int n_omega, int k, const double* Y, SmallWs& ws, uint32_t* status,
+                        hipStream_t s) {
+  const int nc = nchunks(n);
+  const dim3 g(nc, n_omega);
+  double2* part = (double2*)ws.partial;
+  for (int pass = 0; pass < 3; pass++) {
+    hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Y,
+                       pass ? (const double2*)ws.Rinv : (const double2*)nullptr, ws.kmax, nc,
+                       part, pass == 2 ? (const uint32_t*)ws.shifted : (const uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, (int64_t)n, part,
+                       (double2*)ws.R, (double2*)ws.Rinv, pass, ws.shifted, status);
+  }
+}
+
 hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q, SmallWs& ws,
                           uint32_t* status, hipStream_t s) {
-  int nc = nchunks(n);
-  if (nc > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
-  dim3 g(nc, n_omega);
-  double2* part = (double2*)ws.partial;
-  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Y,
-                     (const double2*)nullptr, ws.kmax, nc, part);
-  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
-                     (double2*)ws.R, (double2*)ws.Rinv, 0, status);
-  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Y,
-                     (const double2*)ws.Rinv, ws.kmax, nc, part);
-  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
-                     (double2*)ws.R, (double2*)ws.Rinv, 1, status);
+  if (nchunks(n) > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
+  chol_passes(n, n_omega, k, Y, ws, status, s);
   hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
                      (int64_t)n, k, (const double2*)Y, (const double2*)ws.Rinv, ws.kmax,
                      (double2*)Q);
@@ -369,19 +407,9 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(int k, int kmax, const doubl
 hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const double* Q,
                             double* sigma, double* V, double* Uqu, SmallWs& ws, uint32_t* status,
                             hipStream_t s) {
-  int nc = nchunks(n);
-  if (nc > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
-  dim3 g(nc, n_omega);
-  double2* part = (double2*)ws.partial;
-  // Z = Qz R by two Cholesky QR passes (R and R^-1 composed; Qz never formed)
-  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Z,
-                     (const double2*)nullptr, ws.kmax, nc, part);
-  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
-                     (double2*)ws.R, (double2*)ws.Rinv, 0, status);
-  hipLaunchKernelGGL(k_gram_partial, g, dim3(256), 0, s, (int64_t)n, k, (const double2*)Z,
-                     (const double2*)ws.Rinv, ws.kmax, nc, part);
-  hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, part,
-                     (double2*)ws.R, (double2*)ws.Rinv, 1, status);
+  if (nchunks(n) > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
+  // Z = Qz R by Cholesky QR (R and R^-1 composed; Qz never formed)
+  chol_passes(n, n_omega, k, Z, ws, status, s);
   // W and its product with R^-1 (ws.G holds Tv = R^-1 W)
   hipLaunchKernelGGL(k_jacobi_svd, dim3(n_omega), dim3(256), 0, s, k, ws.kmax,
                      (const double2*)ws.R, (const double2*)ws.Rinv, sigma, (double2*)ws.Ut,

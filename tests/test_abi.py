@@ -111,3 +111,17 @@ def test_factor_bytes_matches_the_layout():
     assert tiles < got < tiles * 1.2
     # FP32 factor: half the tile bytes, one more vector workspace
     assert L.rr_factor_bytes(nx, ny, nw, k, 1, T) < got
+
+
+def test_fp64_fallback_policy_rejects_bad_options_on_the_host():
+    """The failure policy of resolvent() and sweep() is checked before any
+    factorisation, so bad options fail without a GPU."""
+    import paper_1902_01458_amd as rr
+    with pytest.raises(ValueError):
+        rr.resolvent(None, [1.0], k=4, on_failure="retry")
+    with pytest.raises(ValueError):  # the fallback needs factors it owns
+        rr.resolvent(None, [1.0], k=4, precision="mixed", on_failure="fp64", factors=object())
+    with pytest.raises(ValueError):  # and a checked status to act on
+        rr.resolvent(None, [1.0], k=4, precision="mixed", on_failure="fp64", check_status=False)
+    with pytest.raises(ValueError):
+        rr.sweep(None, [1.0], 4, on_failure="retry")

@@ -1,0 +1,109 @@
+"""The failure policy of the mixed-precision path: a pass whose FP32 solves
+cannot be refined (here a shift 1e-7 |lambda| from the rightmost eigenvalue
+of a Burgers operator, kappa(M) = 5e10, so kappa eps_32 >> 1) is refactored
+in FP64 and run again. The FP64 rerun equals a direct FP64 pass bit for bit and
+agrees with the oracle; a mixed pass that converges is left alone."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import resolvent as ores
+from oracle import sketch as osk
+from tests.gpu_util import gain_errors, oracle_problem, to_np
+
+pytestmark = pytest.mark.gpu
+
+CURABLE = (2, 3, 4, 5)  # SINGULAR, NOT_CONVERGED, BREAKDOWN, NONFINITE
+
+
+def rr():
+    import paper_1902_01458_amd as m
+    return m
+
+
+def near_singular():
+    w = W.small("i", 32, 16, nu=1e-2, k=8)
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    lam = np.linalg.eigvals(L.toarray())
+    lam0 = lam[np.argmax(lam.real)]
+    return w, L, phi, -1j * (lam0 + 1e-7 * abs(lam0))
+
+
+def test_resolvent_refactors_in_fp64_when_the_mixed_pass_fails():
+    w, L, phi, omega = near_singular()
+    prob = rr().BurgersProblem.from_workload(w)
+    with pytest.raises(rr().RRError) as e:
+        rr().resolvent(prob, [omega], k=w.k, seed=w.seed, precision="mixed", tile=32)
+    print(f"\nmixed pass without the policy: {e.value}")
+    assert e.value.status in CURABLE
+    del e
+    out = rr().resolvent(prob, [omega], k=w.k, seed=w.seed, precision="mixed", tile=32,
+                         on_failure="fp64")
+    assert out["precision"] == "fp64" and out["fallback_status"] in CURABLE
+    assert out["factors"].precision == "fp64"
+    direct = rr().resolvent(prob, [omega], k=w.k, seed=w.seed, precision="fp64", tile=32)
+    for key in ("sigma_B", "sigma_AV", "V", "U"):
+        np.testing.assert_array_equal(to_np(out[key]), to_np(direct[key]))
+    # an unpivoted FP64 LU of this M (element growth 1.5e3) puts sigma_1 1.2e-8
+    # from the pivoted oracle in a CPU emulation; 1e-6 leaves room for rounding order
+    ref = ores.randomized_resolvent(L, omega, osk.test_matrix(w.n, w.k, phi, w.seed), q=0)
+    eB = gain_errors(to_np(out["sigma_B"])[0], ref.sigma_B).max()
+    eAV = gain_errors(to_np(out["sigma_AV"])[0], ref.sigma_AV).max()
+    print(f"FP64 rerun against the oracle: sigma_B {eB:.1e}, sigma_AV {eAV:.1e}")
+    assert eB <= 1e-6 and eAV <= 1e-6
+    out["factors"].free()
+    direct["factors"].free()
+
+
+def test_policy_leaves_a_converging_mixed_pass_alone():
+    w = W.CONFIGS["cfg0"]
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    prob = rr().BurgersProblem.from_workload(w)
+    out = rr().resolvent(prob, list(w.omegas), k=w.k, q=w.q, seed=w.seed, precision="mixed",
+                         on_failure="fp64")
+    assert out["precision"] == "mixed" and "fallback_status" not in out
+    ref = ores.randomized_resolvent(L, w.omegas[0], osk.test_matrix(w.n, w.k, phi, w.seed), q=w.q)
+    assert gain_errors(to_np(out["sigma_AV"])[0], ref.sigma_AV).max() <= 1e-8
+    out["factors"].free()
+
+
+def test_sweep_redoes_only_the_failed_chunk_in_fp64():
+    w, L, phi, omega = near_singular()
+    oms = [0.5, omega, 2.0]
+    prob = rr().BurgersProblem.from_workload(w)
+    with pytest.raises(rr().RRError):
+        rr().sweep(prob, oms, w.k, seed=w.seed, precision="mixed", chunk=1)
+    out = rr().sweep(prob, oms, w.k, seed=w.seed, precision="mixed", chunk=1, on_failure="fp64")
+    assert out["fp64_chunks"] == [1]
+    direct = rr().sweep(prob, [omega], w.k, seed=w.seed, precision="fp64", chunk=1)
+    np.testing.assert_array_equal(to_np(out["sigma_B"])[1], to_np(direct["sigma_B"])[0])
+    np.testing.assert_array_equal(to_np(out["sigma_AV"])[1], to_np(direct["sigma_AV"])[0])
+    Om = osk.test_matrix(w.n, w.k, phi, w.seed)
+    for i in (0, 2):
+        ref = ores.randomized_resolvent(L, oms[i], Om, q=0)
+        assert gain_errors(to_np(out["sigma_B"])[i], ref.sigma_B).max() <= 1e-8, i
+        assert gain_errors(to_np(out["sigma_AV"])[i], ref.sigma_AV).max() <= 1e-8, i
+
+
+@pytest.mark.parametrize("response", ["av", "qu"])
+def test_cholesky_qr_breakdown_takes_shifted_cholesky_qr3(response):
+    """At the nearly singular shift the sketch Y = H Theta has cond 9e8 (sigma_1
+    1.2e10 against the trailing gains), past the u^-1/2 where the Gram matrix of
+    Cholesky QR stops being numerically positive definite; the first pass is
+    then shifted and a third pass added. With one subspace iteration every
+    orthonormalisation meets it. The basis stays orthonormal to about u cond(Y)
+    and the gains agree with the oracle's Householder QR."""
+    w, L, phi, omega = near_singular()
+    prob = rr().BurgersProblem.from_workload(w)
+    out = rr().resolvent(prob, [omega], k=w.k, q=1, seed=w.seed, precision="fp64", tile=32,
+                         response=response)
+    Q = to_np(out["Q"])[0].T  # (n, k)
+    orth = np.linalg.norm(Q.conj().T @ Q - np.eye(w.k), 2)
+    ref = ores.randomized_resolvent(L, omega, osk.test_matrix(w.n, w.k, phi, w.seed), q=1)
+    eB = gain_errors(to_np(out["sigma_B"])[0], ref.sigma_B).max()
+    print(f"\n||Q^H Q - I|| {orth:.1e}, sigma_B error {eB:.1e}")
+    assert orth <= 1e-6
+    assert eB <= 1e-6
+    if response == "av":
+        assert gain_errors(to_np(out["sigma_AV"])[0], ref.sigma_AV).max() <= 1e-6
+    out["factors"].free()
