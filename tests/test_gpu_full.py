@@ -1,7 +1,10 @@
 """The benchmark's own workload at full size (512 x 256 Burgers, n = 262144,
 16 shifts, k = 20, q = 1) in the launch configuration the benchmark times,
 against the oracle's gains stored by tests/golden/make_golden.py: every gain
-sigma_B (step 5) and sigma_AV (steps 6-8) of every shift."""
+sigma_B (step 5) and sigma_AV (steps 6-8) of every shift; and properties that
+hold at any size: Q and V orthonormal within the Cholesky QR bound
+6 (n k + k (k + 1)) u, unit response modes, and sigma_AV_j >= sigma_B_j
+(||H v_j|| >= ||Q^H H v_j|| for orthonormal Q)."""
 import json
 import os
 
@@ -34,4 +37,19 @@ def test_full_batch_matches_stored_oracle(prec, tol, refine_tol):
     for i in range(len(w.omegas)):
         assert gain_errors(sB[i], gold["sigma_B"][i]).max() <= tol, i
         assert gain_errors(sAV[i], gold["sigma_AV"][i]).max() <= tol, i
+    orth_bound = 6 * (w.n * w.k + w.k * (w.k + 1)) * 2.0 ** -53
+    eye = np.eye(w.k)
+    worst = {"Q": 0.0, "V": 0.0, "U": 0.0}
+    for i in range(len(w.omegas)):
+        for key in ("Q", "V"):
+            X = to_np(out[key][i])  # (k, n): the k columns as rows
+            worst[key] = max(worst[key], np.abs(X @ X.conj().T - eye).max())
+        U = to_np(out["U"][i])
+        worst["U"] = max(worst["U"], np.abs(np.linalg.norm(U, axis=1) - 1).max())
+        big = sB[i] >= 1e-3 * sB[i][0]
+        assert np.all(sAV[i][big] >= sB[i][big] * (1 - tol)), i
+    print(f"\n{prec}: max |Q^H Q - I| {worst['Q']:.1e}, |V^H V - I| {worst['V']:.1e}, "
+          f"| ||u_j|| - 1 | {worst['U']:.1e} (bound {orth_bound:.1e})")
+    assert worst["Q"] <= orth_bound and worst["V"] <= orth_bound
+    assert worst["U"] <= 1e-12
     out["factors"].free()
