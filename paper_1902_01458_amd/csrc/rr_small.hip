@@ -22,11 +22,22 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
 }
 
 // partial[w][chunk] = (Y_c T)^H (Y_c T) over the chunk's rows, where T is the
-// k x k matrix Tm[w] (identity when Tm == NULL).  Y: (n_omega, k, n).  Thread
-// t accumulates the 2 x 2 group of entries (2 t/16 .. +1, 2 (t%16) .. +1) on
-// and above the diagonal (the Cholesky reads the upper triangle only); the
-// sketch width is at most KM = 32, so 256 threads cover every group.
+// k x k matrix Tm[w] (identity when Tm == NULL).  Y: (n_omega, k, n).  The
+// output is cut into 2 x 2 groups on and above the diagonal (the Cholesky
+// reads the upper triangle only); each group is accumulated by S = 256 /
+// groups threads that take every S-th row of a staged sub-block, and their S
+// sums are added in a fixed order at the end, so results are bitwise
+// reproducible.  With Tm, each staged sub-block is first multiplied by T in
+// LDS, every thread taking one row and every fourth column.  The sketch width
+// is at most KM = 32: at most 136 groups, so S >= 1.
 // With only_if != NULL a shift whose only_if[w] is zero is skipped.
+__device__ __forceinline__ void upper_group(int g, int ng, int& gi, int& gj) {
+  int rem = g;
+  gi = 0;
+  while (rem >= ng - gi) { rem -= ng - gi; gi++; }
+  gj = gi + rem;
+}
+
 __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const double2* __restrict__ Y,
                                                       const double2* __restrict__ Tm, int kmax,
                                                       int nchunk, double2* __restrict__ partial,
@@ -40,8 +51,13 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const do
     for (int idx = threadIdx.x; idx < k * k; idx += 256)
       tm[idx / k][idx % k] = Tm[(int64_t)w * kmax * kmax + idx];  // tm[i][j] = T[i][j]
   }
-  const int i0 = 2 * (threadIdx.x / 16), j0 = 2 * (threadIdx.x % 16);
-  const bool act = i0 < k && j0 < k && j0 + 1 >= i0;
+  const int ng = (k + 1) / 2, nup = ng * (ng + 1) / 2, S = 256 / nup;
+  const int t = threadIdx.x;
+  const bool act = t < nup * S;
+  const int g = t % nup, slice = t / nup;
+  int gi, gj;
+  upper_group(g, ng, gi, gj);
+  const int i0 = 2 * gi, j0 = 2 * gj;
   double2 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; a++)
@@ -56,28 +72,30 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const do
       ys[rr][j] = (rr < rows && j < k) ? Yw[(int64_t)j * n + rb + rr] : make_double2(0, 0);
     }
     __syncthreads();
-    if (Tm) {  // ys <- ys * T, one row per thread (the row held in registers)
-      if (threadIdx.x < kSub) {
-        const int rr = threadIdx.x;
-        double2 row[KM];
+    if (Tm) {  // ys <- ys * T: thread (row rr, columns cg + 4 c)
+      const int rr = t % kSub, cg = t / kSub;
+      double2 o[KM / 4];
 #pragma unroll
-        for (int i = 0; i < KM; i++) row[i] = ys[rr][i];
-        for (int j = 0; j < k; j++) {
-          double2 s = make_double2(0, 0);
+      for (int c = 0; c < KM / 4; c++) o[c] = make_double2(0, 0);
+      for (int i = 0; i < k; i++) {
+        const double2 a = ys[rr][i];
 #pragma unroll
-          for (int i = 0; i < KM; i++) {
-            if (i < k) {
-              double2 p = cmul(row[i], tm[i][j]);
-              s.x += p.x; s.y += p.y;
-            }
+        for (int c = 0; c < KM / 4; c++) {
+          const int j = cg + 4 * c;
+          if (j < k) {
+            const double2 p = cmul(a, tm[i][j]);
+            o[c].x += p.x; o[c].y += p.y;
           }
-          ys[rr][j] = s;
         }
       }
       __syncthreads();
+#pragma unroll
+      for (int c = 0; c < KM / 4; c++)
+        if (cg + 4 * c < k) ys[rr][cg + 4 * c] = o[c];
+      __syncthreads();
     }
     if (act) {
-      for (int rr = 0; rr < rows; rr++) {
+      for (int rr = slice; rr < rows; rr += S) {
         const double2 a0 = ys[rr][i0], a1 = ys[rr][i0 + 1];
         const double2 b0 = ys[rr][j0], b1 = ys[rr][j0 + 1];
         double2 p;
@@ -88,14 +106,29 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const do
       }
     }
   }
+  // the S slice sums of every group, added in slice order (S * groups * 4 <=
+  // 1024 entries, staged in ys)
+  __syncthreads();
+  double2* red = &ys[0][0];
   if (act) {
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-      for (int c = 0; c < 2; c++)
-        if (i0 + a < k && j0 + c < k)
-          partial[((int64_t)w * nchunk + chunk) * kmax * kmax + (i0 + a) * k + j0 + c] =
-              acc[a][c];
+      for (int c = 0; c < 2; c++) red[(slice * nup + g) * 4 + a * 2 + c] = acc[a][c];
+  }
+  __syncthreads();
+  for (int e = t; e < nup * 4; e += 256) {
+    const int gg = e / 4, a = (e % 4) / 2, c = e % 2;
+    double2 sum = make_double2(0, 0);
+    for (int sl = 0; sl < S; sl++) {
+      const double2 v = red[(sl * nup + gg) * 4 + e % 4];
+      sum.x += v.x; sum.y += v.y;
+    }
+    int hi, hj;
+    upper_group(gg, ng, hi, hj);
+    const int ii = 2 * hi + a, jj = 2 * hj + c;
+    if (ii < k && jj < k)
+      partial[((int64_t)w * nchunk + chunk) * kmax * kmax + ii * k + jj] = sum;
   }
 }
 
