@@ -107,3 +107,31 @@ def test_cholesky_qr_breakdown_takes_shifted_cholesky_qr3(response):
     if response == "av":
         assert gain_errors(to_np(out["sigma_AV"])[0], ref.sigma_AV).max() <= 1e-6
     out["factors"].free()
+
+
+def test_shifted_cholesky_qr3_on_a_diagonal_operator_with_1e10_gain_spread():
+    """Closed form: for a diagonal L the gains are 1/|i omega - lambda_j|, and
+    with k = n the randomized SVD is exact. One eigenvalue 1e-9 from the
+    shift gives a gain of 7e8 against gains of at most 1 elsewhere, so
+    cond(Y) is about 1e12 and the Gram matrix of Y is far from numerically
+    positive definite. A CPU emulation of the same composed passes leaves Q
+    orthonormal only to u cond(Y) (5e-5) but the gains within 1.1e-9 of the
+    closed form; the test allows 1e-8."""
+    nx = ny = 4
+    n = 2 * nx * ny  # 32: one block row at the 32 tile, k = n
+    lam = -np.concatenate([[1e-9], np.linspace(1.0, 100.0, n - 1)])
+    c = np.zeros((nx, ny, 12))
+    c[..., 0] = lam[0::2].reshape(nx, ny)
+    c[..., 6] = lam[1::2].reshape(nx, ny)
+    prob = rr().BurgersProblem.from_coefficients(c)
+    omega = 1e-9
+    exact = np.sort(1.0 / np.abs(1j * omega - lam))[::-1]
+    out = rr().resolvent(prob, [omega], k=n, q=0, tile=32)
+    Q = to_np(out["Q"])[0].T
+    orth = np.linalg.norm(Q.conj().T @ Q - np.eye(n), 2)
+    eB = gain_errors(to_np(out["sigma_B"])[0], exact).max()
+    eAV = gain_errors(to_np(out["sigma_AV"])[0], exact).max()
+    print(f"\n||Q^H Q - I|| {orth:.1e}; gains against the closed form: sigma_B {eB:.1e}, "
+          f"sigma_AV {eAV:.1e}")
+    assert eB <= 1e-8 and eAV <= 1e-8
+    out["factors"].free()
