@@ -447,18 +447,18 @@ rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power
     const int z = f->tm_zeta <= 0 ? std::min(k, 8) : std::min<int>(f->tm_zeta, k);
     RR_HIP(launch_sketch(opdesc(f), f->phi, k, seed, f->tm_kind, z, f->theta, s));
     if (f->tm_kind == RR_TM_ORTHONORMAL) {  // orthonormal columns, then eq. 10's weights
-      RR_HIP(launch_cholqr2(f->n, 1, k, f->theta, f->theta, f->small, st_word(f), s));
+      RR_HIP(launch_cholqr2(f->n, 1, k, f->theta, f->small, st_word(f), s));
       if (f->phi) RR_HIP(launch_weight_rows(f->n, k, f->phi, f->theta, s));
     }
   }
   const double ts = f->refine_tol_sketch;
   if ((st = solve_any(f, k, 0, f->theta, 0, Q, ts, s)) != RR_OK) return st;         // step 2
-  RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));       // step 3
+  RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, f->small, st_word(f), s));       // step 3
   for (int it = 0; it < power_iters; it++) {                                        // 2.2.1
     if ((st = solve_any(f, k, 1, Q, blk, f->work1, ts, s)) != RR_OK) return st;
-    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, f->work1, f->work1, f->small, st_word(f), s));
+    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, f->work1, f->small, st_word(f), s));
     if ((st = solve_any(f, k, 0, f->work1, blk, Q, ts, s)) != RR_OK) return st;
-    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, Q, f->small, st_word(f), s));
+    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, f->small, st_word(f), s));
   }
   return RR_OK;
 }

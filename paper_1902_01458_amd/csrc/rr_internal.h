@@ -152,11 +152,11 @@ struct SmallWs {   // workspace for tall-skinny reductions
   int nchunk;
   int kmax;
 };
-// CholQR2: Q = Y R^-1 with R upper, real positive diagonal; Q may alias Y.
+// CholQR2 in place: Y <- Q = Y R^-1 with R upper, real positive diagonal.
 // A shift whose Gram matrix is not numerically positive definite takes
 // shifted CholeskyQR3 instead (three passes, the first with a diagonal shift).
-hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q,
-                          SmallWs& ws, uint32_t* status, hipStream_t s);
+hipError_t launch_cholqr2(int n, int n_omega, int k, double* Y, SmallWs& ws, uint32_t* status,
+                          hipStream_t s);
 // Z = Qz R (CholQR2, or shifted CholQR3 as above); SVD of R^H = Ut S W^H; sigma = S; V = Z R^-1 W;
 // if Uqu != NULL also Uqu = Q Ut.
 hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const double* Q,

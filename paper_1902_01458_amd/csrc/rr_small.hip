@@ -259,12 +259,15 @@ __global__ __launch_bounds__(256) void k_chol(int k, int kmax, int nchunk, int64
 }
 
 // Out = Y * Tm[w]  (n x k times k x k), one row per thread (held in registers);
-// Out may alias Y.
+// Out may alias Y.  With only_if != NULL a shift whose only_if[w] is zero is
+// skipped.
 __global__ __launch_bounds__(256) void k_apply_small(int64_t n, int k, const double2* Y,
                                                      const double2* __restrict__ Tm, int kmax,
-                                                     double2* Out) {
+                                                     double2* Out,
+                                                     const uint32_t* __restrict__ only_if) {
   __shared__ double2 tm[KM][KM];
   const int w = blockIdx.y;
+  if (only_if && only_if[w] == 0) return;
   for (int idx = threadIdx.x; idx < k * k; idx += 256)
     tm[idx / k][idx % k] = Tm[(int64_t)w * kmax * kmax + idx];
   __syncthreads();
@@ -288,14 +291,28 @@ __global__ __launch_bounds__(256) void k_apply_small(int64_t n, int k, const dou
   }
 }
 
+// T[w] = I for the shifts with only_if[w] set.
+__global__ __launch_bounds__(256) void k_identity_if(int k, int kmax, double2* Tm,
+                                                     const uint32_t* __restrict__ only_if) {
+  const int w = blockIdx.x;
+  if (only_if[w] == 0) return;
+  for (int idx = threadIdx.x; idx < k * k; idx += 256)
+    Tm[(int64_t)w * kmax * kmax + idx] = make_double2(idx / k == idx % k ? 1.0 : 0.0, 0.0);
+}
+
 static int nchunks(int64_t n) { return (int)((n + kChunkRows - 1) / kChunkRows); }
 
 // Cholesky QR of Y (n_omega blocks of n x k) into ws.R and ws.Rinv: two
 // passes, and for shifts whose first Cholesky broke down a shifted first pass
 // and a third (shifted CholeskyQR3).  The launch sequence is the same either
-// way (the third pass returns at once for the other shifts).
-static void chol_passes(int n, int n_omega, int k, const double* Y, SmallWs& ws, uint32_t* status,
-                        hipStream_t s) {
+// way (the third pass returns at once for the other shifts).  With
+// explicit_q, a shifted shift's Y is replaced by Q1 = Y R1^-1 after the first
+// pass and its R^-1 reset to I, so the two passes that follow orthonormalise
+// Q1 itself and the final Q = Q1 R^-1 is orthonormal to O(u); otherwise Q is
+// formed from Y through the composed R^-1 and orthonormal to about u cond(Y).
+// R is the composed factor (Y = Q R) either way.
+static void chol_passes(int n, int n_omega, int k, double* Y, bool explicit_q, SmallWs& ws,
+                        uint32_t* status, hipStream_t s) {
   const int nc = nchunks(n);
   const dim3 g(nc, n_omega);
   double2* part = (double2*)ws.partial;
@@ -305,16 +322,23 @@ static void chol_passes(int n, int n_omega, int k, const double* Y, SmallWs& ws,
                        part, pass == 2 ? (const uint32_t*)ws.shifted : (const uint32_t*)nullptr);
     hipLaunchKernelGGL(k_chol, dim3(n_omega), dim3(256), 0, s, k, ws.kmax, nc, (int64_t)n, part,
                        (double2*)ws.R, (double2*)ws.Rinv, pass, ws.shifted, status);
+    if (pass == 0 && explicit_q) {
+      hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
+                         (int64_t)n, k, (const double2*)Y, (const double2*)ws.Rinv, ws.kmax,
+                         (double2*)Y, (const uint32_t*)ws.shifted);
+      hipLaunchKernelGGL(k_identity_if, dim3(n_omega), dim3(256), 0, s, k, ws.kmax,
+                         (double2*)ws.Rinv, (const uint32_t*)ws.shifted);
+    }
   }
 }
 
-hipError_t launch_cholqr2(int n, int n_omega, int k, const double* Y, double* Q, SmallWs& ws,
-                          uint32_t* status, hipStream_t s) {
+hipError_t launch_cholqr2(int n, int n_omega, int k, double* Y, SmallWs& ws, uint32_t* status,
+                          hipStream_t s) {
   if (nchunks(n) > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
-  chol_passes(n, n_omega, k, Y, ws, status, s);
+  chol_passes(n, n_omega, k, Y, true, ws, status, s);
   hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
                      (int64_t)n, k, (const double2*)Y, (const double2*)ws.Rinv, ws.kmax,
-                     (double2*)Q);
+                     (double2*)Y, (const uint32_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -442,18 +466,19 @@ hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const do
                             hipStream_t s) {
   if (nchunks(n) > ws.nchunk || k > ws.kmax || k > KM) return hipErrorInvalidValue;
   // Z = Qz R by Cholesky QR (R and R^-1 composed; Qz never formed)
-  chol_passes(n, n_omega, k, Z, ws, status, s);
+  chol_passes(n, n_omega, k, const_cast<double*>(Z), false, ws, status, s);  // Z is not written
   // W and its product with R^-1 (ws.G holds Tv = R^-1 W)
   hipLaunchKernelGGL(k_jacobi_svd, dim3(n_omega), dim3(256), 0, s, k, ws.kmax,
                      (const double2*)ws.R, (const double2*)ws.Rinv, sigma, (double2*)ws.Ut,
                      (double2*)ws.W, (double2*)ws.G, status);
   // V = Z R^-1 W = Qz W
   hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
-                     (int64_t)n, k, (const double2*)Z, (const double2*)ws.G, ws.kmax, (double2*)V);
+                     (int64_t)n, k, (const double2*)Z, (const double2*)ws.G, ws.kmax, (double2*)V,
+                     (const uint32_t*)nullptr);
   if (Uqu)  // Halko et al.'s response modes U = Q Ut (eq. 8)
     hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
                        (int64_t)n, k, (const double2*)Q, (const double2*)ws.Ut, ws.kmax,
-                       (double2*)Uqu);
+                       (double2*)Uqu, (const uint32_t*)nullptr);
   return hipGetLastError();
 }
 
