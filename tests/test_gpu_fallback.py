@@ -165,3 +165,34 @@ def test_gmres_ir_carries_the_mixed_pipeline_through_the_resonance():
                        refine_method="gmres", gmres_restart=12, refine_iters=10,
                        refine_tol=1e-10, refine_tol_sketch=1e-10)
     assert e.value.status == 3
+
+
+def test_graph_replay_through_the_shifted_passes_equals_the_eager_pass():
+    """A captured FP64 pass (refactorisation included) at the nearly singular
+    shift next to an ordinary one, with one subspace iteration: the flag-gated
+    launches of shifted CholeskyQR3 (the shifted retry, Q1, the third pass)
+    replay bit for bit what the eager calls compute, with eager work and
+    synchronisations between the replays."""
+    import torch
+    w, L, phi, omega = near_singular()
+    oms = [omega, 1.3]
+    prob = rr().BurgersProblem.from_workload(w)
+    f = rr().factor(prob, oms, "fp64", k_max=w.k, tile=32)
+    Q = f.sketch_solve(w.k, w.seed, 1)
+    Z = f.adjoint_solve(Q)
+    ref = f.gains(Q, Z, "av")
+    f.check()
+    ref = {key: to_np(v) for key, v in ref.items() if v is not None}
+    ref["Q"] = to_np(Q)
+    g = rr().capture(f, w.k, w.seed, 1, "av", refactor=True)
+    X = torch.randn((2, 3, w.n), dtype=torch.complex128, device="cuda")
+    for rep in range(3):
+        Y = prob.apply(oms, X)
+        torch.cuda.synchronize()
+        assert torch.isfinite(torch.view_as_real(Y)).all()
+        out = g.launch()
+        f.check()
+        for key in ("sigma_B", "sigma_AV", "V", "U", "Q"):
+            np.testing.assert_array_equal(to_np(out[key]), ref[key])
+    g.free()
+    f.free()
