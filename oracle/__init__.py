@@ -9,7 +9,7 @@ It follows Ribeiro, Yeh & Taira, "Randomized resolvent analysis"
 (arXiv:1902.01458): Algorithm 1 (randomized resolvent analysis), Section 2.2
 (sketch, orthonormal basis, projection, reduced SVD, recovery of the response
 modes through eq. (9)), Section 2.2.1 (power / subspace iteration) and
-Section 3.3 / eq. (10) (physics-informed test matrix).  All arithmetic is
+Section 3.4 / eq. (10) (physics-informed test matrix).  All arithmetic is
 complex128 / float64 on the CPU with NumPy and SciPy library primitives (LAPACK
 band LU, SuperLU, Householder QR, SVD) used as whole steps, never re-blocked.
 

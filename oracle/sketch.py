@@ -1,6 +1,6 @@
 """Physics-informed complex Gaussian test matrix (Algorithm 1 step 1, eq. 10).
 
-Algorithm 1 draws a random normal test matrix; Section 3.3 scales its rows by
+Algorithm 1 draws a random normal test matrix; Section 3.4 scales its rows by
 Phi, the 2-norm of the base-flow velocity gradient at each grid point, stacked
 over the variables (eq. 10: Omega_p = diag(Phi) Omega).  With the base flow
 (U, V = 0) the gradient tensor has a single non-zero row, so its 2-norm is

@@ -3,7 +3,7 @@ persistent factor launch, read back through the rr_factor_schedule hook).
 
 The unpivoted band LU of a block-banded matrix with B tiles each side of the
 diagonal (the no-fill factorisation the method's direct solves rest on,
-Sec. 3.3) updates tile (r, t) as A_rt -= sum_s L_rs U_st over
+Sec. 3.1) updates tile (r, t) as A_rt -= sum_s L_rs U_st over
 s in [max(0, max(r, t) - B), min(r, t) - 1], then finalises it against the
 LU of diagonal tile m = min(r, t).  The launch splits each off-diagonal tile
 into an early task E (all updates but the last, written as a partial tile)

@@ -1,5 +1,5 @@
 """Test-matrix variants of Algorithm 1 step 1 on the GPU (Section 2.2.2 and
-3.3): the device generator against the oracle's, the pipeline per kind
+3.4): the device generator against the oracle's, the pipeline per kind
 against the oracle, and the k-convergence study against the dense SVD."""
 import numpy as np
 import pytest
@@ -58,7 +58,8 @@ def test_pipeline_per_kind_matches_oracle(kind):
 
 
 def test_k_convergence_and_test_matrices_against_dense_svd():
-    """Section 3.3 at n = 1024 (nu = 1e-3, omega = 1, q = 0): the error of
+    """The k study of Section 3.2 (Fig. 7) and the test-matrix comparison of
+    Section 3.4 at n = 1024 (nu = 1e-3, omega = 1, q = 0): the error of
     sigma_1 (eq. 9) and of the leading response pair against the dense SVD
     for k = 2 .. 32 and each test matrix, Phi-weighted (eq. 10) and, for the
     Gaussian one, plain.  Every kind converges: the error at k = 32 is below

@@ -83,3 +83,35 @@ def test_gradient_is_phase_invariant():
     b = grad.gradient(2.0, u * ph, v * ph, w.nx, w.ny, hx, hy)
     np.testing.assert_allclose(a[0], b[0], atol=1e-13 * np.abs(a[0]).max())
     assert abs(a[1] - b[1]) < 1e-12 * abs(a[1]) and abs(a[2] - b[2]) < 1e-12 * (abs(a[2]) + 1)
+
+
+def test_ring_terms_match_bruteforce():
+    # every node of the (nx+2, ny+2) array, ring included: the term-by-term
+    # formula against the node-by-node differentiation of the coefficients
+    w, U, hx, hy = problem()
+    rng = np.random.Generator(np.random.PCG64(8))
+    u = rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n)
+    v = rng.standard_normal(w.n) + 1j * rng.standard_normal(w.n)
+    g, dnu, dom = grad.gradient_full(1.3, u, v, w.nx, w.ny, hx, hy)
+    gb = grad.gradient_bruteforce(1.3, u, v, U, w.nx, w.ny, hx, hy, w.nu, ring=True)
+    np.testing.assert_allclose(g, gb, rtol=1e-12, atol=1e-12 * np.abs(gb).max())
+    assert np.abs(g[0, 1:-1]).max() > 0 and np.abs(g[1:-1, -1]).max() > 0
+    assert g[0, 0] == g[0, -1] == g[-1, 0] == g[-1, -1] == 0.0
+    g0, dnu0, dom0 = grad.gradient(1.3, u, v, w.nx, w.ny, hx, hy)
+    np.testing.assert_array_equal(g[1:-1, 1:-1], g0)
+    assert (dnu, dom) == (dnu0, dom0)
+
+
+def test_ring_formula_matches_finite_differences_of_exact_gain():
+    w, U, hx, hy = problem()
+    omega = 0.9
+    s, Ud, Vd = sigma1(U, w.nx, w.ny, hx, hy, w.nu, omega)
+    g, _, _ = grad.gradient_full(s[0], Ud[:, 0], Vd[:, 0], w.nx, w.ny, hx, hy)
+    h = 1e-6
+    for (i, j) in [(0, 2), (w.nx + 1, 3), (4, 0), (2, w.ny + 1), (0, 0)]:
+        Up, Um = U.copy(), U.copy()
+        Up[i, j] += h
+        Um[i, j] -= h
+        fd = (sigma1(Up, w.nx, w.ny, hx, hy, w.nu, omega)[0][0]
+              - sigma1(Um, w.nx, w.ny, hx, hy, w.nu, omega)[0][0]) / (2 * h)
+        assert abs(fd - g[i, j]) <= 1e-6 * np.abs(g).max(), (i, j, fd, g[i, j])

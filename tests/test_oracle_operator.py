@@ -123,3 +123,49 @@ def test_singular_shift_detected():
     for be in ("gb", "splu"):
         with pytest.raises(SingularShift):
             ShiftedSolver(M, be)
+
+
+def test_anisotropic_grid_closed_form():
+    # h_x != h_y (0.5 against 0.6) and U = x^2 + 3y, whose central differences
+    # are exact: U_x = 2x, U_y = 3, Phi = sqrt(4x^2 + 9) + 0.1.  A swap of h_x
+    # and h_y anywhere in the coefficients or the weights fails here.
+    from oracle import sketch
+    nx, ny, nu = 5, 4, 0.3
+    dom = (0.0, 3.0, -1.0, 2.0)
+    hx, hy, X, Y = grid_fields(nx, ny, dom)
+    assert abs(hx - 0.5) < 1e-15 and abs(hy - 0.6) < 1e-15
+    U = X ** 2 + 3.0 * Y
+    c = op.burgers_coefficients(U, nx, ny, hx, hy, nu)
+    x = X[1:-1, 1:-1]
+    Ui = U[1:-1, 1:-1]
+    ax, ay = nu / hx ** 2, nu / hy ** 2
+    want = np.empty_like(c)
+    want[..., 0] = -2 * (ax + ay) - 2 * x
+    want[..., 1] = ax - Ui / (2 * hx)
+    want[..., 2] = ax + Ui / (2 * hx)
+    want[..., 3] = want[..., 4] = ay
+    want[..., 5] = -3.0
+    want[..., 6] = -2 * (ax + ay)
+    want[..., 7] = want[..., 1]
+    want[..., 8] = want[..., 2]
+    want[..., 9] = want[..., 10] = ay
+    want[..., 11] = 0.0
+    np.testing.assert_allclose(c, want, rtol=1e-13, atol=1e-13)
+    phi = sketch.gradient_weight(U, hx, hy)
+    np.testing.assert_allclose(phi, np.sqrt(4 * x ** 2 + 9) + 0.1, rtol=1e-14)
+
+
+def test_anisotropic_diffusion_directions():
+    # nu = 1, U = 0 on h_x = 0.5, h_y = 0.6: L x^2 = 2 and L y^2 = 2 at nodes
+    # whose stencil is interior; with the spacings swapped they would be
+    # 2 (0.6/0.5)^2 and 2 (0.5/0.6)^2
+    nx, ny = 7, 6
+    hx, hy, X, Y = grid_fields(nx, ny, (0.0, 4.0, -1.0, 3.2))
+    assert abs(hx - 0.5) < 1e-15 and abs(hy - 0.6) < 1e-15
+    L = op.assemble(op.burgers_coefficients(np.zeros((nx + 2, ny + 2)), nx, ny, hx, hy, 1.0))
+    for f in (X ** 2, Y ** 2):
+        q = np.zeros(2 * nx * ny)
+        q[0::2] = f[1:-1, 1:-1].ravel()
+        q[1::2] = f[1:-1, 1:-1].ravel()
+        r = (L @ q).reshape(nx, ny, 2)
+        np.testing.assert_allclose(r[1:-1, 1:-1], 2.0, rtol=1e-11)
