@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-shifts", type=int, default=1)
+    ap.add_argument("--no-cpu-1-thread", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the single-shift, 64-shift and 1024 x 512 rates")
+    ap.add_argument("--no-cfg4", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -92,15 +96,25 @@ def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, gr
         step()
     f.check()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    # per step: the factor kernel alone and the step's last main solve launch
+    # (the forward solve of the eq. 9 recovery), recorded by the library
+    kev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for e in kev:
+        for x in e:
+            x.record(stream)  # creates the events before the library records them
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
+        f.set_timing_events(factor=(kev[i][0], kev[i][1]), solve=(kev[i][2], kev[i][3]))
         step(evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    f.set_timing_events()
     f.check()
     per = {nm: float(np.mean([e[c].elapsed_time(e[c + 1]) for e in evs]))
            for c, nm in enumerate(names)}
+    kern = {"factor": float(np.mean([e[0].elapsed_time(e[1]) for e in kev])),
+            "solve": float(np.mean([e[2].elapsed_time(e[3]) for e in kev]))}
     # the optional steps 10-11 (not part of the timed step), on the last outputs
     sv = f.resvd(outs["U"], outs["V"], scale=outs["sigma_AV"])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -109,7 +123,8 @@ def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, gr
     e1.record(stream)
     f.check()
     resvd_ms = e0.elapsed_time(e1)
-    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "factor_ms": per["factor"], "calls_ms": per,
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "factor_ms": kern["factor"],
+           "solve_ms": kern["solve"], "calls_ms": per,
            "sigma_B": outs["sigma_B"].cpu().numpy(), "sigma_AV": outs["sigma_AV"].cpu().numpy(),
            "refine": f.refine_count(), "bytes": f.nbytes(), "tune": tune,
            "optional_svd_ms": resvd_ms}
@@ -130,6 +145,91 @@ def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, gr
     del Q, Z, outs
     torch.cuda.empty_cache()
     return res
+
+
+def timed_pass(f, k, seed, q, reps):
+    """Mean event-timed ms of `reps` passes of Algorithm 1 (refactorisation,
+    sketch and subspace iteration, adjoint solve, gains with the eq. 9
+    recovery) on the handle, after one warm-up pass."""
+    import torch
+    stream = torch.cuda.current_stream()
+    Q = f.empty_block(k)
+    Z = f.empty_block(k)
+    outs = {}
+
+    def one():
+        f.refactor()
+        f.sketch_solve(k, seed, q, out=Q)
+        f.adjoint_solve(Q, out=Z)
+        outs.update(f.gains(Q, Z, "av", out=outs))
+
+    one()
+    f.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        one()
+    e1.record(stream)
+    f.check()
+    return e0.elapsed_time(e1) / reps, outs
+
+
+def extras(args):
+    """The other rates the benchmark plan asks for, each a timed pass after a
+    warm-up: the single shift omega = 2 of the 512 x 256 configuration, the
+    64-shift sweep of config 2 (mixed and FP64) and config 4's 16 shifts in
+    chunks that fit the device (mixed; allocation outside the timed passes)."""
+    import torch
+
+    import paper_1902_01458_amd as rr
+    import workloads as W
+    out = {}
+    w1 = W.CONFIGS["cfg1"]
+    p1 = rr.BurgersProblem.from_workload(w1)
+    for prec, tol in (("mixed", args.refine_tol), ("fp64", 0.0)):
+        f = rr.factor(p1, [2.0], prec, k_max=w1.k, refine_tol=tol)
+        ms, o = timed_pass(f, w1.k, w1.seed, w1.q, 3)
+        out.setdefault("single_omega2_ms", {})[prec] = ms
+        f.free()
+    del p1
+    w2 = W.CONFIGS["cfg2"]
+    p2 = rr.BurgersProblem.from_workload(w2)
+    gold2 = os.path.join(ROOT, "tests", "golden", "cfg2_oracle.json")
+    g2 = json.load(open(gold2)) if os.path.exists(gold2) else None
+    for prec, tol in (("mixed", args.refine_tol), ("fp64", 0.0)):
+        f = rr.factor(p2, list(w2.omegas), prec, k_max=w2.k, refine_tol=tol)
+        ms, o = timed_pass(f, w2.k, w2.seed, w2.q, 2)
+        err = None
+        if g2 is not None:
+            sb = np.asarray(g2["sigma_B"])[:, 0]
+            err = float(np.max(np.abs(o["sigma_B"][:, 0].cpu().numpy() - sb) / sb))
+        out.setdefault("cfg2_64shifts", {})[prec] = {
+            "ms_per_pass": ms, "omega_solves_per_s": len(w2.omegas) / (ms * 1e-3),
+            "sigma1_rel_err_vs_oracle": err}
+        f.free()
+        torch.cuda.empty_cache()
+    del p2
+    if not args.no_cfg4:
+        w4 = W.CONFIGS["cfg4"]
+        p4 = rr.BurgersProblem.from_workload(w4)
+        free, _ = torch.cuda.mem_get_info()
+        per = rr.factor_bytes(w4.nx, w4.ny, 1, w4.k, "mixed") + 6 * w4.k * w4.n * 16
+        chunk = max(1, min(16, int(0.8 * free // per)))
+        total = 0.0
+        s1 = []
+        for c0 in range(0, 16, chunk):
+            oms = list(w4.omegas[c0:c0 + chunk])
+            f = rr.factor(p4, oms, "mixed", k_max=w4.k, refine_tol=args.refine_tol)
+            ms, o = timed_pass(f, w4.k, w4.seed, w4.q, 1)
+            total += ms
+            s1 += list(o["sigma_AV"][:, 0].cpu().numpy())
+            del o
+            f.free()
+            torch.cuda.empty_cache()
+        out["cfg4_16shifts_mixed"] = {"chunk": chunk, "ms_total": total,
+                                      "omega_solves_per_s": 16 / (total * 1e-3),
+                                      "sigma1_AV_first": float(s1[0])}
+    return out
 
 
 TRAFFIC = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -160,7 +260,7 @@ def accuracy(res, gold):
     return float(np.max(np.abs(res["sigma_B"][:, 0] - sb) / sb))
 
 
-def cpu_baseline(w, shifts):
+def cpu_baseline(w, shifts, threads1=True):
     """The oracle (Algorithm 1 in FP64 on the host) on `shifts` of the batch."""
     import threadpoolctl
 
@@ -180,9 +280,28 @@ def cpu_baseline(w, shifts):
         for om in sel:
             ores.randomized_resolvent(L, om, Om, q=w.q)
         dt = time.perf_counter() - t0
-    return {"value": len(sel) / dt, "unit": "ω-solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sel)} of {len(w.omegas)} shifts (omega={sel[0]:.3g}) of the same "
-                      f"workload, SuperLU factor + 5 solves + QR + SVD in FP64, {dt:.1f} s"}
+    res = {"value": len(sel) / dt, "unit": "ω-solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"{len(sel)} of {len(w.omegas)} shifts (omega={sel[0]:.3g}) of the same "
+                     f"workload, SuperLU factor + 5 solves + QR + SVD in FP64, {dt:.1f} s"}
+    if threads1:
+        with threadpoolctl.threadpool_limits(1):
+            t0 = time.perf_counter()
+            ores.randomized_resolvent(L, sel[0], Om, q=w.q)
+            res["value_1_thread"] = 1.0 / (time.perf_counter() - t0)
+    model = mem = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal"):
+                mem = f"{int(ln.split()[1]) / 2**20:.0f} GiB"
+                break
+    except OSError:
+        pass
+    res["cpu_model"], res["host_memory"] = model, mem
+    return res
 
 
 def main():
@@ -210,9 +329,6 @@ def main():
     b = 2 * w.ny
     n_om = len(w.omegas)
     flops = 8.0 * w.n * b * b * n_om  # algorithmic band-LU flops per launch (all shifts)
-    # algorithmic bytes of one FP64 solve launch: the factors once (n (2b+1)
-    # complex entries per shift), the right-hand sides in and the solutions out
-    solve_bytes = n_om * (w.n * (2 * b + 1) * 16 + 2 * w.k * w.n * 16)
     auto = not args.no_autotune
     mixed = run_path(prob, w, "mixed", args.steps, args.warmup, args.tile, args.refine_iters,
                      auto, args.graph_reps, args.refine_tol)
@@ -227,6 +343,19 @@ def main():
     value = n_om / (mixed["ms_per_step"] * 1e-3)
     ach = flops / (mixed["factor_ms"] * 1e-3) / 1e12
     fk = f"k_factor<float,{mixed['tune']['tile']}>"
+    # algorithmic bytes of one solve launch: the factor once (n (2b+1) entries
+    # per shift, FP32 or FP64), the right-hand sides in and the solutions out
+    # (FP64 complex, the caller's blocks)
+    def solve_roofline(res, esize, name):
+        byt = n_om * (w.n * (2 * b + 1) * esize + 2 * w.k * w.n * 16)
+        bw = byt / (res["solve_ms"] * 1e-3) / 1e9
+        np_ = 16 * ((w.k + 15) // 16)
+        return {"bound": "hbm", "achieved": bw, "peak": 8000.0, "unit": "GB/s",
+                "frac": bw / 8000.0, "bytes_per_launch": byt,
+                "traffic": traffic(f"k_ssolve<{name},{res['tune']['tile']},{np_},false>"),
+                "kernel": f"k_ssolve<{name},{res['tune']['tile']},{np_},false> (forward solve of "
+                          f"the eq. 9 recovery, all {n_om} shifts x {w.k} columns, one launch)",
+                "launch_ms": res["solve_ms"]}
     line = {
         "metric": METRIC, "value": value, "unit": "ω-solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
@@ -247,11 +376,10 @@ def main():
                      "frac": ach / PEAK["mixed"], "traffic": traffic(fk),
                      "kernel": f"{fk} (band LU of all {n_om} shifts, one launch)",
                      "launch_ms": mixed["factor_ms"]},
+        "roofline_solve_fp32": solve_roofline(mixed, 8, "float"),
     }
     if fp64 is not None:
         a64 = flops / (fp64["factor_ms"] * 1e-3) / 1e12
-        sk = f"k_solve2<double,{fp64['tune']['tile']},16,true>"
-        bw = solve_bytes / (fp64["calls_ms"]["adjoint"] * 1e-3) / 1e9
         line["fp64"] = {"value": n_om / (fp64["ms_per_step"] * 1e-3),
                         "ms_per_step": fp64["ms_per_step"], "calls_ms": fp64["calls_ms"],
                         "optional_svd_ms": fp64["optional_svd_ms"],
@@ -260,15 +388,16 @@ def main():
                         "sigma1_rel_err_vs_oracle": accuracy(fp64, gold),
                         "factor_roofline": {"bound": "mfma", "achieved": a64,
                                             "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                                            "frac": a64 / PEAK["fp64"]}}
-        line["roofline_solve"] = {"bound": "hbm", "achieved": bw, "peak": 8000.0, "unit": "GB/s",
-                                  "frac": bw / 8000.0, "traffic": traffic(sk),
-                                  "kernel": f"{sk} (adjoint solve, FP64, all {n_om} shifts x "
-                                            f"{w.k} columns, one launch)",
-                                  "launch_ms": fp64["calls_ms"]["adjoint"]}
+                                            "frac": a64 / PEAK["fp64"],
+                                            "launch_ms": fp64["factor_ms"]}}
+        line["roofline_solve"] = solve_roofline(fp64, 16, "double")
         line["mixed_over_fp64"] = line["fp64"]["ms_per_step"] / mixed["ms_per_step"]
+    if not args.no_extras:
+        line["extras"] = extras(args)
+        print(f"# extras: {line['extras']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_shifts)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_shifts,
+                                            threads1=not args.no_cpu_1_thread)
     print(json.dumps(line), flush=True)
 
 

@@ -145,6 +145,14 @@ typedef struct {
                             blocks of n_omega*k_max*n complex FP64 (not
                             counted by rr_factor_bytes)                        */
   int32_t gmres_restart; /* steps per GMRES-IR correction, 1 .. 16 (default 8) */
+  int32_t superblock;    /* block rows (tiles) a solve step takes at once: the
+                            sweeps of every solve walk superblocks of this many
+                            block rows, x_S = D_S^-1 (b_S - sum T x), with the
+                            inverses D_S^-1 of the superblocks' diagonal blocks
+                            formed after each factorisation.  1 .. 8; 0 = the
+                            default (256 rows per step, at most the half-band's
+                            tiles); negative = one block row per step (the
+                            tile-by-tile recurrence with chain tiles)          */
 } rr_tuning;
 
 enum { RR_REFINE_PLAIN = 0, RR_REFINE_GMRES = 1 };
@@ -263,7 +271,11 @@ rr_status rr_resvd(rr_factors* f, int32_t k, const double* Us, const double* sca
  * problem (U != NULL).  sigma1: device n_omega; u1, v1: device n_omega vectors
  * of n complex (response, forcing), at stride `vec_stride` complex elements
  * between shifts (k*n for the first column of a (n_omega, k, n) block);
- * dU: device n_omega*nx*ny; dnu, domega: device n_omega each. */
+ * dU: device n_omega*(nx+2)*(ny+2), the derivative with respect to every
+ * value of the base-flow array U in U's own layout (index i*(ny+2)+j), ring
+ * included: a ring value enters L through the central difference U_x or U_y
+ * of its one interior neighbour (corners: zero); dnu, domega: device n_omega
+ * each. */
 rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const double* v1,
                   int64_t vec_stride, double* dU, double* dnu, double* domega, void* stream);
 
@@ -274,6 +286,27 @@ rr_status rr_check(rr_factors* f, void* stream);
 /* Largest number of correction steps any mixed-precision solve needed since
  * the previous rr_check (0 for FP64); valid after rr_check. */
 int32_t rr_refine_count(rr_factors* f);
+
+/* Timing hook: HIP events (hipEvent_t, or NULL for none) that later calls on
+ * this handle record on their stream right before and right after the band
+ * factorisation kernel (rr_factor's and rr_refactor's launch of the first 64
+ * shifts; not the flag fill or the superblock inverses) and the main solve
+ * launch of every solve call (the first FP32 or FP64 solve of a logical
+ * solve, with its two small counter fills, not the refinement corrections),
+ * so that one kernel's duration can be measured inside a timed pass.  The
+ * caller keeps the events alive while they are set; passing NULLs clears
+ * them.  Host only; RR_ERR_INVALID for a NULL handle. */
+rr_status rr_set_timing_events(rr_factors* f, void* factor_begin, void* factor_end,
+                               void* solve_begin, void* solve_end);
+
+/* Sweep cap of the one-sided Jacobi SVD of the k x k factor (Algorithm 1
+ * step 5, and step 10 in rr_resvd); default 40, in [1, 64].  A sweep that
+ * still rotates a pair at the cap latches RR_ERR_NOT_CONVERGED (reported by
+ * rr_check; the gains and modes are then those of the last sweep).  Host
+ * only; RR_ERR_INVALID for a NULL handle or a value out of range (the
+ * setting is then unchanged).  Lowering it is how the non-convergence
+ * report is tested. */
+rr_status rr_set_jacobi_sweeps(rr_factors* f, int32_t sweeps);
 
 /* Device bytes held by the handle. */
 size_t rr_bytes(const rr_factors* f);

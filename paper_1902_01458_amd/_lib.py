@@ -21,7 +21,8 @@ EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sket
            "rr_adjoint_solve", "rr_solve", "rr_gains", "rr_resvd", "rr_grad", "rr_check", "rr_refine_count",
            "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
-           "rr_sketch", "rr_factor_schedule", "rr_set_test_matrix")
+           "rr_sketch", "rr_factor_schedule", "rr_set_test_matrix", "rr_set_jacobi_sweeps",
+           "rr_set_timing_events")
 
 
 class RRError(RuntimeError):
@@ -45,7 +46,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("refine_tol_sketch", ctypes.c_double), ("refine_method", ctypes.c_int32),
-                ("gmres_restart", ctypes.c_int32)]
+                ("gmres_restart", ctypes.c_int32), ("superblock", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,6 +85,8 @@ def lib() -> ctypes.CDLL:
                           ctypes.c_uint32, vp],
         "rr_sketch": [pp, i32, u64, ctypes.c_int, i32, vp, vp],
         "rr_set_test_matrix": [vp, ctypes.c_int, i32],
+        "rr_set_jacobi_sweeps": [vp, i32],
+        "rr_set_timing_events": [vp, vp, vp, vp, vp],
         "rr_factor_bytes": [i32, i32, i32, i32, ctypes.c_int, i32],
         "rr_factor_schedule": [i32, i32, vp, i64],
         "rr_set_allocator": [ALLOC_FN, FREE_FN, vp],

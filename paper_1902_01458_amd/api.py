@@ -127,7 +127,7 @@ class Factors:
                  tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
                  refine_tol_sketch: float = 0.0, stream=None, discount: float = 0.0,
                  test_matrix: str = "gaussian", zeta: int = 0, refine_method: str = "plain",
-                 gmres_restart: int = 0):
+                 gmres_restart: int = 0, superblock: int = 0):
         # discount beta: the paper's discounted resolvent (Section 2.1),
         # M = i omega I - (L - beta I), i.e. the shift omega - i beta here
         om = np.asarray(omegas, dtype=np.complex128).reshape(-1) - 1j * discount
@@ -142,8 +142,9 @@ class Factors:
         im = np.ascontiguousarray(om.imag)
         # refine_method "gmres": GMRES-IR corrections (mixed precision), for
         # shifts where plain refinement with the FP32 LU stalls
+        # superblock: block rows per solve step (0: default, < 0: one at a time)
         tune = _lib.Tuning(tile, grid, refine_iters, refine_tol, refine_tol_sketch,
-                           _lib.REFINE_METHODS[refine_method], gmres_restart)
+                           _lib.REFINE_METHODS[refine_method], gmres_restart, superblock)
         ps = prob.c_struct()
         check(lib().rr_factor(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
                               im.ctypes.data_as(ctypes.c_void_p), self.n_omega, k_max,
@@ -157,6 +158,21 @@ class Factors:
         "rademacher", "sparse" (zeta nonzeros per row, 0: min(k, 8)) or
         "orthonormal"; each weighted by the problem's Phi (eq. 10) if set."""
         check(lib().rr_set_test_matrix(self.handle, _lib.TEST_MATRICES[kind], zeta))
+
+    def set_timing_events(self, factor=None, solve=None):
+        """Record torch.cuda.Event pairs (begin, end) around the factorisation
+        kernel and the main launch of every solve call (rr_set_timing_events);
+        None clears a pair.  The events must outlive their use."""
+        def raw(ev):
+            return ctypes.c_void_p(ev.cuda_event) if ev is not None else None
+        fb, fe = factor if factor is not None else (None, None)
+        sb, se = solve if solve is not None else (None, None)
+        check(lib().rr_set_timing_events(self.handle, raw(fb), raw(fe), raw(sb), raw(se)))
+
+    def set_jacobi_sweeps(self, sweeps: int):
+        """Sweep cap of the k x k Jacobi SVD (default 40); a sweep that still
+        rotates at the cap is reported as RR_ERR_NOT_CONVERGED by check()."""
+        check(lib().rr_set_jacobi_sweeps(self.handle, sweeps))
 
     # -- lifetime ----------------------------------------------------------
     def free(self):
@@ -248,9 +264,10 @@ class Factors:
 
     def grad(self, sigma1: torch.Tensor, u1: torch.Tensor, v1: torch.Tensor, stride: int,
              stream=None):
-        """(dU (n_omega, nx, ny), dnu (n_omega,), domega (n_omega,)) of sigma_1."""
+        """(dU (n_omega, nx+2, ny+2), dnu (n_omega,), domega (n_omega,)) of
+        sigma_1; dU covers every node of the base-flow array, ring included."""
         nx, ny = self.prob.nx, self.prob.ny
-        dU = torch.empty((self.n_omega, nx, ny), dtype=torch.float64, device="cuda")
+        dU = torch.empty((self.n_omega, nx + 2, ny + 2), dtype=torch.float64, device="cuda")
         dnu = torch.empty(self.n_omega, dtype=torch.float64, device="cuda")
         dom = torch.empty(self.n_omega, dtype=torch.float64, device="cuda")
         check(lib().rr_grad(self.handle, ctypes.c_void_p(sigma1.data_ptr()),

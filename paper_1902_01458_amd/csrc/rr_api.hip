@@ -72,7 +72,8 @@ rr_status dalloc(rr_factors* f, T** p, size_t bytes) {
 }
 
 void free_all(rr_factors* f) {
-  void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->flags, f->ctrl, f->theta,
+  void* ps[] = {f->coef, f->phi, f->U, f->omega, f->tiles, f->xs, f->cbuf, f->flags, f->ctrl,
+                f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
                 f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->small.shifted, f->grad_partial,
                 f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial};
@@ -120,7 +121,7 @@ hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStr
   hipError_t e = launch_fill_u32((uint32_t*)g.H, 0u, (int64_t)n_omega * k * (m + 1) * m * 4, s);
   auto solve32 = [&](const double* in, double* out) {
     return launch_solve(f->geom, f->n, n_omega, k, true, f->tiles, adjoint, in, blk, out, f->xs,
-                        f->flags, ticket_word(f), st_word(f), f->solve_grid, s, skip);
+                        f->cbuf, f->flags, ticket_word(f), st_word(f), f->solve_grid, s, skip);
   };
   if (e == hipSuccess) e = solve32(r, V(0));
   if (e == hipSuccess)
@@ -147,8 +148,10 @@ hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStr
 rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t bstride,
                     double* X, double tol, hipStream_t s) {
   const bool mixed = f->prec == RR_MIXED;
+  if (f->tev[2]) RR_HIP(hipEventRecord(f->tev[2], s));
   RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
-                      f->xs, f->flags, ticket_word(f), st_word(f), f->solve_grid, s));
+                      f->xs, f->cbuf, f->flags, ticket_word(f), st_word(f), f->solve_grid, s));
+  if (f->tev[3]) RR_HIP(hipEventRecord(f->tev[3], s));
   if (!mixed || tol >= 1.0) return RR_OK;  // a tolerance of 1 or more asks for no correction
   double* res = f->work3;
   RR_HIP(launch_fill_u32(conv_word(f), 0u, 1, s));
@@ -161,12 +164,12 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
       RR_HIP(gmres_correction(f, k, adjoint, res, s));
     } else {
       RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
-                          (int64_t)k * f->n, res, f->xs, f->flags, ticket_word(f), st_word(f),
-                          f->solve_grid, s, conv_word(f)));
+                          (int64_t)k * f->n, res, f->xs, f->cbuf, f->flags, ticket_word(f),
+                          st_word(f), f->solve_grid, s, conv_word(f)));
     }
     RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
-    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, it, f->small, st_word(f),
-                                fail_word(f), s, conv_word(f)));
+    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, it, adjoint, f->small,
+                                st_word(f), fail_word(f), s, conv_word(f)));
     hipLaunchKernelGGL(k_refine_step, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
                        f->ctrl + 4 + it, conv_word(f));
   }
@@ -179,24 +182,34 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
 // Device allocations of a handle, in one place for rr_factor and rr_factor_bytes.
 struct Plan {
   BandGeom geom;
-  size_t coef, phi, U, omega, tiles, xs, flags, ctrl, theta, vec, work3, partial, kk2, rho, shifted,
-      grad;
+  size_t coef, phi, U, omega, tiles, xs, cbuf, flags, ctrl, theta, vec, work3, partial, kk2, rho,
+      shifted, grad;
   int nchunk, grad_nchunk;
   size_t nflags;
   size_t total() const {
-    return coef + phi + U + omega + tiles + xs + flags + ctrl + theta + 2 * vec + work3 + partial +
-           5 * kk2 + rho + shifted + grad;
+    return coef + phi + U + omega + tiles + xs + cbuf + flags + ctrl + theta + 2 * vec + work3 +
+           partial + 5 * kk2 + rho + shifted + grad;
   }
 };
 
+// Block rows per superblock solve step: `want` > 0 as asked (at most 8), 0
+// the default (256 rows: 4 tiles of 64, 8 of 32, at most the half-band's
+// tiles), < 0 the tile-by-tile solve (0 returned).
+int superblock_tiles(int want, int T, int B) {
+  if (want < 0) return 0;
+  if (want > 0) return std::min(want, 8);
+  return std::max(1, std::min(B, 256 / T));
+}
+
 Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T, bool has_phi,
-               bool has_U) {
+               bool has_U, int sb) {
   Plan pl{};
   const int64_t n = 2 * (int64_t)nx * ny;
   const size_t nn = (size_t)nx * ny;
   pl.geom.T = T;
   pl.geom.B = (2 * ny + T - 1) / T;
   pl.geom.NB = (int)((n + T - 1) / T);
+  pl.geom.P = superblock_tiles(sb, T, pl.geom.B);
   const size_t elem = prec == RR_MIXED ? 2 * sizeof(float) : 2 * sizeof(double);
   pl.coef = nn * 12 * sizeof(double);
   pl.phi = has_phi ? nn * sizeof(double) : 0;
@@ -204,7 +217,9 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   pl.omega = 2 * (size_t)n_omega * sizeof(double);
   pl.tiles = (size_t)n_omega * pl.geom.tiles_per_omega() * T * T * elem;
   pl.xs = (size_t)n_omega * pl.geom.NB * T * solve_np(k_max) * 2 * sizeof(double);
-  pl.nflags = std::max((size_t)n_omega * pl.geom.tiles_per_omega(), (size_t)n_omega * pl.geom.NB);
+  pl.cbuf = (size_t)n_omega * std::max(pl.geom.P, 1) * T * solve_np(k_max) * 2 * sizeof(double);
+  pl.nflags = std::max({(size_t)n_omega * pl.geom.tiles_per_omega(), (size_t)n_omega * pl.geom.NB,
+                        (size_t)ssolve_counters(pl.geom, n_omega)});
   pl.flags = pl.nflags * sizeof(int);
   pl.ctrl = 64 * sizeof(uint32_t);
   pl.theta = (size_t)k_max * n * 2 * sizeof(double);
@@ -214,9 +229,9 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   const size_t kk = (size_t)std::max(k_max * k_max, 64);
   pl.partial = (size_t)n_omega * pl.nchunk * kk * 2 * sizeof(double);
   pl.kk2 = (size_t)n_omega * kk * 2 * sizeof(double);
-  pl.rho = prec == RR_MIXED ? (size_t)n_omega * 64 * sizeof(double) : 0;
+  pl.rho = prec == RR_MIXED ? (size_t)n_omega * kRhoStride * sizeof(double) : 0;
   pl.shifted = (size_t)n_omega * sizeof(uint32_t);
-  pl.grad_nchunk = (int)((nn + 255) / 256);
+  pl.grad_nchunk = (int)(((size_t)(nx + 2) * (ny + 2) + 255) / 256);  // k_grad's blocks
   pl.grad = (size_t)n_omega * pl.grad_nchunk * 2 * sizeof(double);
   return pl;
 }
@@ -293,6 +308,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   if (tune && tune->refine_method == RR_REFINE_GMRES &&
       (tune->gmres_restart < 0 || tune->gmres_restart > kGmresMaxRestart))
     return fail(RR_ERR_INVALID, "gmres_restart out of range");
+  if (tune && tune->superblock > 8) return fail(RR_ERR_INVALID, "superblock must be <= 8");
   if (!is_dev_ptr(p->coef) || (p->phi && !is_dev_ptr(p->phi)) || (p->U && !is_dev_ptr(p->U)))
     return fail(RR_ERR_INVALID, "coef/phi/U must be device pointers");
 
@@ -311,6 +327,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->geom.T = T;
   f->geom.B = (b + T - 1) / T;
   f->geom.NB = (f->n + T - 1) / T;
+  f->geom.P = superblock_tiles(tune ? tune->superblock : 0, T, f->geom.B);
   f->grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
   f->solve_grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
   f->refine_iters = tune && tune->refine_iters ? tune->refine_iters : 6;
@@ -324,7 +341,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   hipStream_t s = (hipStream_t)stream;
   const size_t nn = (size_t)p->nx * p->ny;
   const Plan pl = make_plan(p->nx, p->ny, n_omega, k_max, prec, T, p->phi != nullptr,
-                            p->U != nullptr);
+                            p->U != nullptr, tune ? tune->superblock : 0);
   f->tile_bytes = pl.tiles;
   rr_status st = RR_OK;
 #define ALLOC(ptr, bytes)                      \
@@ -338,6 +355,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   ALLOC(f->omega, pl.omega);
   ALLOC(f->tiles, pl.tiles);
   ALLOC(f->xs, pl.xs);
+  ALLOC(f->cbuf, pl.cbuf);
   ALLOC(f->flags, pl.flags);
   f->flag_count = pl.nflags;
   ALLOC(f->ctrl, pl.ctrl);
@@ -426,7 +444,10 @@ rr_status rr_refactor(rr_factors* f, void* stream) {
   if (f->sticky_hip_error) return fail(RR_ERR_HIP, "handle is unusable after a HIP error");
   hipError_t e = launch_factor(opdesc(f), f->geom, f->omega, f->n_omega, f->prec == RR_MIXED,
                                f->tiles, f->flags, factor_counters(f), st_word(f), f->grid,
-                               (hipStream_t)stream);
+                               (hipStream_t)stream, f->tev);
+  // a new factor: the refinement's measured contractions no longer hold
+  if (e == hipSuccess && f->small.rho)
+    e = launch_refine_reset(f->n_omega, f->small.rho, (hipStream_t)stream);
   if (e != hipSuccess) {
     f->sticky_hip_error = true;
     return fail(RR_ERR_HIP, std::string("factor launch: ") + hipGetErrorString(e));
@@ -574,6 +595,9 @@ rr_status rr_check(rr_factors* f, void* stream) {
   if (w & ST_SINGULAR) return fail(RR_ERR_SINGULAR, "zero or non-finite pivot in the band LU");
   if (w & ST_NONFINITE) return fail(RR_ERR_NONFINITE, "non-finite values in the results");
   if (w & ST_BREAKDOWN) return fail(RR_ERR_BREAKDOWN, "Gram matrix not positive definite");
+  if (w & ST_SVD_NOT_CONVERGED)
+    return fail(RR_ERR_NOT_CONVERGED, "the k x k Jacobi SVD did not converge in " +
+                                          std::to_string(f->small.jacobi_sweeps) + " sweeps");
   if (w & ST_NOT_CONVERGED) {
     std::string m = "refinement did not converge (most unconverged columns after each correction:";
     for (int it = 0; it < f->refine_iters; it++) m += " " + std::to_string(ctrl[4 + it]);
@@ -583,6 +607,23 @@ rr_status rr_check(rr_factors* f, void* stream) {
 }
 
 int32_t rr_refine_count(rr_factors* f) { return f ? f->refine_used : 0; }
+
+rr_status rr_set_timing_events(rr_factors* f, void* factor_begin, void* factor_end,
+                               void* solve_begin, void* solve_end) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  f->tev[0] = (hipEvent_t)factor_begin;
+  f->tev[1] = (hipEvent_t)factor_end;
+  f->tev[2] = (hipEvent_t)solve_begin;
+  f->tev[3] = (hipEvent_t)solve_end;
+  return RR_OK;
+}
+
+rr_status rr_set_jacobi_sweeps(rr_factors* f, int32_t sweeps) {
+  if (!f) return fail(RR_ERR_INVALID, "NULL handle");
+  if (sweeps < 1 || sweeps > 64) return fail(RR_ERR_INVALID, "sweeps must be in [1, 64]");
+  f->small.jacobi_sweeps = sweeps;
+  return RR_OK;
+}
 
 size_t rr_bytes(const rr_factors* f) { return f ? f->bytes : 0; }
 
@@ -607,7 +648,7 @@ size_t rr_factor_bytes(int32_t nx, int32_t ny, int32_t n_omega, int32_t k_max, r
   if (nx < 1 || ny < 1 || n_omega < 1 || k_max < 1 || k_max > 32) return 0;
   const int T = tile ? tile : 64;
   if (T != 32 && T != 64) return 0;
-  return make_plan(nx, ny, n_omega, k_max, prec, T, true, true).total();
+  return make_plan(nx, ny, n_omega, k_max, prec, T, true, true, 0).total();
 }
 
 // ---------------------------------------------------------------------------

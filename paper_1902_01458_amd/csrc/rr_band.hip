@@ -703,7 +703,8 @@ __device__ __forceinline__ void stage_store(const Acc2<R>& acc, cplx<R>* stage, 
 // Block-inverse LU of diagonal tile s (lu_blockinv), kept beside the chain tiles.
 template <typename R, int T>
 __device__ __forceinline__ cplx<R>* lub_ptr(const FactorParams& P, int w, int s) {
-  return chain_ptr<R, T>(P, w, s, BandGeom::kChain);
+  int64_t idx = ((int64_t)w * P.g.NB + s) * P.g.row_tiles() + P.g.lub_index();
+  return reinterpret_cast<cplx<R>*>(P.tiles) + idx * (T * T);
 }
 
 // Diagonal flags: 1 = partial (E done), 2 = block-inverse LU published,
@@ -798,8 +799,9 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     int* dflag = flag_ptr(P, w, m, m);
     if (tk.kind >= 2) {
       // chain tiles of diagonal tile m: L_mm^-1 L_m,m-dd (kind 2) or
-      // U_m-dd,m U_mm^-1 (kind 3), dd = 1 .. kChainD, with D_m in LDS
-      if (m == 0) continue;
+      // U_m-dd,m U_mm^-1 (kind 3), dd = 1 .. kChainD, with D_m in LDS; only
+      // the tile-by-tile solve reads them
+      if (m == 0 || P.g.P > 0) continue;
       wait_inputs(P, w, m, m, 0, -1, dflag, FL_DIAG_INV);
       tile_to_lds<R, T>(tile_ptr<R, T>(P, w, m, m), lds);
       __syncthreads();
@@ -849,7 +851,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     __syncthreads();
     lds_to_tile<R, T>(lds, X, rowmajor);
     publish(flag_ptr(P, w, r, t), FL_FINAL);
-    if (d > BandGeom::kChainD) continue;
+    if (d > BandGeom::kChainD || P.g.P > 0) continue;
     // 4. chain tile with the full inverse D of tile m (the new tile is in LDS)
     const cplx<R>* D = tile_ptr<R, T>(P, w, m, m);
     wait_inputs(P, w, r, t, 0, -1, dflag, FL_DIAG_INV);
@@ -867,15 +869,104 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
   }
 }
 
+// Tile `slot` of block row r's superblock-inverse area (BandGeom::sb_slot).
+template <typename R, int T>
+__device__ __forceinline__ cplx<R>* sb_ptr(const FactorParams& P, int w, int r, int slot) {
+  int64_t idx = ((int64_t)w * P.g.NB + r) * P.g.row_tiles() + P.g.sb_index(slot);
+  return reinterpret_cast<cplx<R>*>(P.tiles) + idx * (T * T);
+}
+
+// Off-diagonal tiles of the inverses of each superblock's diagonal block (the
+// block triangles L-hat and U-hat of P block rows), after the factorisation:
+//   L-hat^-1:  X_jj = L_jj^-1,  X_ij = -L_ii^-1 sum_{l=j}^{i-1} L_il X_lj   (i > j)
+//   U-hat^-1:  X_jj = U_jj^-1,  X_ij = -U_ii^-1 sum_{l=i+1}^{j} U_il X_lj   (i < j)
+// (block forward / back substitution on the identity).  One workgroup per
+// (shift, superblock, triangle, column j) walks its column outward from the
+// diagonal; each tile it writes is read back by the later ones after a
+// barrier (same workgroup, same CU).  Products are T x T tile GEMMs on MFMA
+// with operands from memory; the sum is staged in LDS for the product with
+// the diagonal inverse.
+template <typename R, int T>
+__global__ __launch_bounds__(FGeom<T>::NT) void k_sbinv(FactorParams P) {
+  typedef FGeom<T> G;
+  constexpr int KQ = sizeof(R) == 8 ? 4 : 8;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<R>* sacc = reinterpret_cast<cplx<R>*>(smem_raw);  // T x LDT, column-major
+  cplx<R>* stage = sacc + T * G::LDT;
+  const int PS = P.g.P, NB = P.g.NB, NS = P.g.NS(), B = P.g.B;
+  const int wave = threadIdx.x >> 6;
+  const int rb = wave / G::CPR, cp = wave % G::CPR;
+  int64_t id = blockIdx.x;
+  const int c = (int)(id % (PS - 1));
+  id /= PS - 1;
+  const int upper = (int)(id % 2);
+  id /= 2;
+  const int S = (int)(id % NS), w = (int)(id / NS);
+  const int s0 = S * PS;
+  Acc2<R> acc;
+  if (!upper) {
+    const int j = c;
+    if (s0 + j >= NB) return;
+    const cplx<R>* Djj = tile_ptr<R, T>(P, w, s0 + j, s0 + j);
+    for (int i = j + 1; i < PS && s0 + i < NB; i++) {
+      acc.zero();
+      for (int l = j; l < i; l++) {
+        if (i - l > B) continue;  // outside the band: L_il = 0
+        const cplx<R>* X = l == j ? Djj : sb_ptr<R, T>(P, w, s0 + l, sb_slot(l, j));
+        tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + l), T, false, MK_NONE,
+                                   X, T, true, l == j ? MK_UNIT_LOWER : MK_NONE, rb, cp);
+      }
+      __syncthreads();
+      acc_to_lds<R, T>(acc, sacc, false, rb, cp);
+      __syncthreads();
+      acc.zero();
+      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false,
+                                MK_UNIT_LOWER, sacc, G::LDT, true, MK_NONE, rb, cp);
+      stage_store<R, T>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), false, rb, cp);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  } else {
+    const int j = c + 1;
+    if (s0 + j >= NB) return;
+    const cplx<R>* Djj = tile_ptr<R, T>(P, w, s0 + j, s0 + j);
+    for (int i = j - 1; i >= 0; i--) {
+      acc.zero();
+      for (int l = i + 1; l <= j; l++) {
+        if (l - i > B) continue;  // outside the band: U_il = 0
+        const cplx<R>* X = l == j ? Djj : sb_ptr<R, T>(P, w, s0 + l, sb_slot(l, j));
+        tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + l), T, true, MK_NONE,
+                                   X, T, l == j, l == j ? MK_UPPER : MK_NONE, rb, cp);
+      }
+      __syncthreads();
+      acc_to_lds<R, T>(acc, sacc, false, rb, cp);
+      __syncthreads();
+      acc.zero();
+      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false, MK_UPPER,
+                                sacc, G::LDT, true, MK_NONE, rb, cp);
+      stage_store<R, T>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), true, rb, cp);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+}
+
 template <typename R, int T>
 constexpr size_t factor_lds() {
   return sizeof(cplx<R>) * 2 * (size_t)T * FGeom<T>::LDT;
 }
 
 template <typename R, int T>
-static hipError_t launch_factor_t(const FactorParams& P, int grid, hipStream_t s) {
+static hipError_t launch_factor_t(const FactorParams& P, int grid, hipStream_t s,
+                                  const hipEvent_t* ev) {
   const size_t lds = factor_lds<R, T>();
+  if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_factor<R, T>), dim3(grid), dim3(FGeom<T>::NT), lds, s, P);
+  if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
+  if (P.g.P > 1) {  // the superblocks' diagonal inverses, for the superblock solve
+    const int64_t nblk = (int64_t)P.n_omega * P.g.NS() * 2 * (P.g.P - 1);
+    hipLaunchKernelGGL((k_sbinv<R, T>), dim3((unsigned)nblk), dim3(FGeom<T>::NT), lds, s, P);
+  }
   return hipGetLastError();
 }
 
@@ -885,14 +976,25 @@ hipError_t prepare_factor(int T, bool fp32) {
   auto set = [](const void* fn, size_t lds) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   };
+  hipError_t e = hipErrorInvalidValue;
   if (fp32) {
-    if (T == 64) return set((const void*)k_factor<float, 64>, factor_lds<float, 64>());
-    if (T == 32) return set((const void*)k_factor<float, 32>, factor_lds<float, 32>());
+    if (T == 64) {
+      e = set((const void*)k_factor<float, 64>, factor_lds<float, 64>());
+      if (e == hipSuccess) e = set((const void*)k_sbinv<float, 64>, factor_lds<float, 64>());
+    } else if (T == 32) {
+      e = set((const void*)k_factor<float, 32>, factor_lds<float, 32>());
+      if (e == hipSuccess) e = set((const void*)k_sbinv<float, 32>, factor_lds<float, 32>());
+    }
   } else {
-    if (T == 64) return set((const void*)k_factor<double, 64>, factor_lds<double, 64>());
-    if (T == 32) return set((const void*)k_factor<double, 32>, factor_lds<double, 32>());
+    if (T == 64) {
+      e = set((const void*)k_factor<double, 64>, factor_lds<double, 64>());
+      if (e == hipSuccess) e = set((const void*)k_sbinv<double, 64>, factor_lds<double, 64>());
+    } else if (T == 32) {
+      e = set((const void*)k_factor<double, 32>, factor_lds<double, 32>());
+      if (e == hipSuccess) e = set((const void*)k_sbinv<double, 32>, factor_lds<double, 32>());
+    }
   }
-  return hipErrorInvalidValue;
+  return e;
 }
 
 // Shifts per launch: every shift of a launch holds one diagonal worker for the
@@ -902,7 +1004,7 @@ constexpr int kMaxShiftsPerLaunch = 64;
 
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega, int n_omega,
                          bool fp32, void* tiles, int* flags, uint32_t* counters,
-                         uint32_t* status, int grid, hipStream_t s) {
+                         uint32_t* status, int grid, hipStream_t s, const hipEvent_t* ev) {
   const int slots = factor_slots(g.B);
   const size_t tile_bytes = (size_t)g.T * g.T * (fp32 ? 8 : 16);
   hipError_t e = launch_fill_u32((uint32_t*)flags, 0u, (int64_t)n_omega * g.tiles_per_omega(), s);
@@ -917,12 +1019,12 @@ hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omeg
     int gr = grid > P.total ? (int)P.total : grid;
     gr += nw;  // the diagonal workers
     if (fp32) {
-      if (g.T == 64) e = launch_factor_t<float, 64>(P, gr, s);
-      else if (g.T == 32) e = launch_factor_t<float, 32>(P, gr, s);
+      if (g.T == 64) e = launch_factor_t<float, 64>(P, gr, s, w0 == 0 ? ev : nullptr);
+      else if (g.T == 32) e = launch_factor_t<float, 32>(P, gr, s, w0 == 0 ? ev : nullptr);
       else e = hipErrorInvalidValue;
     } else {
-      if (g.T == 64) e = launch_factor_t<double, 64>(P, gr, s);
-      else if (g.T == 32) e = launch_factor_t<double, 32>(P, gr, s);
+      if (g.T == 64) e = launch_factor_t<double, 64>(P, gr, s, w0 == 0 ? ev : nullptr);
+      else if (g.T == 32) e = launch_factor_t<double, 32>(P, gr, s, w0 == 0 ? ev : nullptr);
       else e = hipErrorInvalidValue;
     }
   }

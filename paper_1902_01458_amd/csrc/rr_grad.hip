@@ -6,7 +6,11 @@
 //   d sigma / domega = sigma^2 Im(v^H u)
 // L depends on the interior nodal U through the convection coefficient at the
 // node itself and through the central differences U_x, U_y at its four
-// neighbours; dL/dnu is the Dirichlet Laplacian on both components.
+// neighbours; a value on the boundary ring enters only through the central
+// difference of its one interior neighbour (U_x for the west / east ring,
+// U_y for the south / north ring; the corners through none); dL/dnu is the
+// Dirichlet Laplacian on both components.  dU covers the whole
+// (nx+2) x (ny+2) base-flow array, ring included, in U's own layout.
 #include "rr_internal.h"
 
 namespace rr {
@@ -20,7 +24,9 @@ __device__ __forceinline__ double im_cmulc(double2 a, double2 b) {  // Im(conj(a
   return a.x * b.y - a.y * b.x;
 }
 
-// One thread per interior node p = j + ny*i; u, v of shift w at stride.
+// One thread per node q = J + (ny+2)*I of the (nx+2) x (ny+2) array (ring
+// included); interior nodes are p = (J-1) + ny*(I-1).  u, v of shift w at
+// stride.
 __global__ __launch_bounds__(kGradBlock) void k_grad(int nx, int ny, double hx, double hy,
                                                      const double* __restrict__ sigma1,
                                                      const double2* __restrict__ u1,
@@ -29,14 +35,35 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(int nx, int ny, double hx, 
                                                      double* __restrict__ partial, int nchunk) {
   __shared__ double red[2][kGradBlock];
   const int w = blockIdx.y;
-  const int nn = nx * ny;
-  const int p = blockIdx.x * kGradBlock + threadIdx.x;
+  const int NY = ny + 2;
+  const int nfull = (nx + 2) * NY;
+  const int q = blockIdx.x * kGradBlock + threadIdx.x;
   const double2* u = u1 + (int64_t)w * stride;
   const double2* v = v1 + (int64_t)w * stride;
   double s2 = sigma1[w] * sigma1[w];
   double lap_part = 0.0, vu_part = 0.0;
-  if (p < nn) {
-    int i = p / ny, j = p % ny;
+  const double ihx = 1.0 / (2.0 * hx), ihy = 1.0 / (2.0 * hy);
+  const int I = q / NY, J = q % NY;
+  const bool ring = q < nfull && (I == 0 || I == nx + 1 || J == 0 || J == ny + 1);
+  if (ring) {
+    // the one interior neighbour whose U_x (west / east) or U_y (south /
+    // north) reads this node; corners have none
+    double g = 0.0;
+    const bool cornerless = (I == 0 || I == nx + 1) != (J == 0 || J == ny + 1);
+    if (cornerless) {
+      if (I == 0 || I == nx + 1) {  // U_x(nb) = (U(E) - U(W)) / 2hx; C carries -U_x
+        const int p = (J - 1) + ny * (I == 0 ? 0 : nx - 1);
+        const double sgn = I == 0 ? 1.0 : -1.0;
+        g = sgn * re_cmulc(v[2 * p], u[2 * p]) * ihx;
+      } else {                      // U_y(nb) = (U(N) - U(S)) / 2hy; Cpl = -U_y
+        const int p = (J == 0 ? 0 : ny - 1) + ny * (I - 1);
+        const double sgn = J == 0 ? 1.0 : -1.0;
+        g = sgn * re_cmulc(v[2 * p], u[2 * p + 1]) * ihy;
+      }
+    }
+    dU[(int64_t)w * nfull + q] = s2 * g;
+  } else if (q < nfull) {
+    const int i = I - 1, j = J - 1, p = j + ny * i;
     bool hE = i < nx - 1, hW = i > 0, hN = j < ny - 1, hS = j > 0;
     int pE = p + ny, pW = p - ny, pN = p + 1, pS = p - 1;
     const double2 z = make_double2(0, 0);
@@ -46,7 +73,6 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(int nx, int ny, double hx, 
     double2 uvN = hN ? u[2 * pN + 1] : z, uvS = hS ? u[2 * pS + 1] : z;
     double2 vuE = hE ? v[2 * pE] : z, vuW = hW ? v[2 * pW] : z;
     double2 vuN = hN ? v[2 * pN] : z, vuS = hS ? v[2 * pS] : z;
-    double ihx = 1.0 / (2.0 * hx), ihy = 1.0 / (2.0 * hy);
     // -U_p d/dx on both components at p
     double g = -re_cmulc(vu, make_double2((uuE.x - uuW.x) * ihx, (uuE.y - uuW.y) * ihx))
                - re_cmulc(vv, make_double2((uvE.x - uvW.x) * ihx, (uvE.y - uvW.y) * ihx));
@@ -54,15 +80,14 @@ __global__ __launch_bounds__(kGradBlock) void k_grad(int nx, int ny, double hx, 
     g += -re_cmulc(vuW, uuW) * ihx + re_cmulc(vuE, uuE) * ihx;
     // -U_y v at S and N
     g += -re_cmulc(vuS, uvS) * ihy + re_cmulc(vuN, uvN) * ihy;
-    dU[(int64_t)w * nn + p] = s2 * g;
+    dU[(int64_t)w * nfull + q] = s2 * g;
     // Re(v^H Lap u) and Im(v^H u) contributions of rows 2p, 2p+1
     double2 uuN = hN ? u[2 * pN] : z, uuS = hS ? u[2 * pS] : z;
     double ax = 1.0 / (hx * hx), ay = 1.0 / (hy * hy);
     double2 lu = make_double2(ax * (uuE.x + uuW.x - 2 * uu.x) + ay * (uuN.x + uuS.x - 2 * uu.x),
                               ax * (uuE.y + uuW.y - 2 * uu.y) + ay * (uuN.y + uuS.y - 2 * uu.y));
-    double2 uvNn = uvN, uvSs = uvS;
-    double2 lv = make_double2(ax * (uvE.x + uvW.x - 2 * uv.x) + ay * (uvNn.x + uvSs.x - 2 * uv.x),
-                              ax * (uvE.y + uvW.y - 2 * uv.y) + ay * (uvNn.y + uvSs.y - 2 * uv.y));
+    double2 lv = make_double2(ax * (uvE.x + uvW.x - 2 * uv.x) + ay * (uvN.x + uvS.x - 2 * uv.x),
+                              ax * (uvE.y + uvW.y - 2 * uv.y) + ay * (uvN.y + uvS.y - 2 * uv.y));
     lap_part = re_cmulc(vu, lu) + re_cmulc(vv, lv);
     vu_part = im_cmulc(vu, uu) + im_cmulc(vv, uv);
   }
@@ -101,8 +126,8 @@ hipError_t launch_grad(int nx, int ny, double hx, double hy, int n_omega, const 
                        double* dU, double* dnu, double* domega, double* partial, int nchunk,
                        hipStream_t s) {
   (void)omega;
-  int nn = nx * ny;
-  int nc = (nn + kGradBlock - 1) / kGradBlock;
+  int nfull = (nx + 2) * (ny + 2);
+  int nc = (nfull + kGradBlock - 1) / kGradBlock;
   if (nc > nchunk) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_grad, dim3(nc, n_omega), dim3(kGradBlock), 0, s, nx, ny, hx, hy, sigma1,
                      (const double2*)u1, (const double2*)v1, stride, dU, partial, nc);

@@ -20,6 +20,7 @@ enum : uint32_t {
   ST_BREAKDOWN = 1u << 2,
   ST_NONFINITE = 1u << 3,
   ST_TIMEOUT = 1u << 4,
+  ST_SVD_NOT_CONVERGED = 1u << 5,  // the k x k Jacobi SVD still rotated at its sweep cap
 };
 
 // Wall-clock bound of any dataflow wait (constant 100 MHz counter ticks).
@@ -85,16 +86,33 @@ struct BandGeom {  // tile geometry of the band factor
   int T;     // tile edge
   int B;     // tiles per half-band: ceil(b / T)
   int NB;    // block rows: ceil(n / T)
-  // Block row s stores its 2B+1 band tiles (s, s-B) .. (s, s+B), then the
-  // kChain chain tiles of the solves' recurrences, then the diagonal tile's
-  // LU with inverted 16 x 16 diagonal blocks, read only by the
-  // factorisation itself (rr_band.hip).
+  int P = 0; // superblock: P consecutive block rows solved as one step
+             // (rr_ssolve.hip); 0 = the tile-by-tile solve (rr_solve.hip)
+  // Block row s stores its 2B+1 band tiles (s, s-B) .. (s, s+B), then, for
+  // the tile-by-tile solve only (P = 0), the kChain chain tiles of its
+  // recurrences, then the diagonal tile's LU with inverted 16 x 16 diagonal
+  // blocks, read only by the factorisation itself (rr_band.hip), then
+  // (P > 1) P - 1 tiles of the inverses of its superblock's diagonal block
+  // (sb_slot below).
   static constexpr int kChainD = 3;            // neighbour distances with chain tiles
   static constexpr int kChain = 4 * kChainD;   // chain_index() below
-  static constexpr int kAux = kChain + 1;      // tiles after the band per block row
-  __host__ __device__ int row_tiles() const { return 2 * B + 1 + kAux; }
+  __host__ __device__ int chain_tiles() const { return P > 0 ? 0 : kChain; }
+  __host__ __device__ int sb_slots() const { return P > 1 ? P - 1 : 0; }
+  __host__ __device__ int lub_index() const { return 2 * B + 1 + chain_tiles(); }
+  __host__ __device__ int sb_index(int slot) const { return lub_index() + 1 + slot; }
+  __host__ __device__ int row_tiles() const { return lub_index() + 1 + sb_slots(); }
   __host__ __device__ int64_t tiles_per_omega() const { return (int64_t)NB * row_tiles(); }
+  __host__ __device__ int NS() const { return P > 0 ? (NB + P - 1) / P : 0; }  // superblocks
 };
+
+// Superblock S holds block rows s0 = S P .. s0 + P - 1.  Its diagonal block
+// is block-lower L-hat (tiles L_ij, j <= i) times block-upper U-hat; the
+// factorisation's last pass stores the off-diagonal tiles of their inverses:
+// (L-hat^-1)_ij, j < i, column-major like L tiles, and (U-hat^-1)_ij, j > i,
+// row-major like U tiles, in block row s0 + i, at aux slot j (L) or j - 1
+// (U); the diagonal tiles of both inverses are the diagonal tile's own
+// [U^-1 | L^-1].
+__host__ __device__ inline int sb_slot(int i, int j) { return j < i ? j : j - 1; }
 
 // Chain tiles of block row s (formed by the factorisation, read by the
 // solves): one kind per sweep, for the neighbours at distance d = 1 .. kChainD.
@@ -123,9 +141,12 @@ hipError_t launch_weight_rows(int64_t n, int k, const double* phi, double* Theta
 // Band LU: tiles = n_omega * tiles_per_omega() tiles of T*T complex (R = float|double).
 // counters: two device words (task tickets, diagonal-worker roles); the launch
 // has grid + n_omega workgroups.
+// ev (optional, two events): recorded right before and after the first
+// factor kernel launch (timing of that kernel alone).
 hipError_t launch_factor(const OpDesc& op, const BandGeom& g, const double* omega,
                          int n_omega, bool fp32, void* tiles, int* flags, uint32_t* counters,
-                         uint32_t* status, int grid, hipStream_t s);
+                         uint32_t* status, int grid, hipStream_t s,
+                         const hipEvent_t* ev = nullptr);
 // Dynamic-LDS attributes of the factor / solve kernels for one tile and
 // precision; called when a handle is created, never on the launch path.
 hipError_t prepare_factor(int T, bool fp32);
@@ -133,13 +154,24 @@ hipError_t prepare_solve(int T, bool fp32);
 // Multi-RHS solve with the band factor: X = M^-1 Bm (adjoint: M^-H Bm).
 // Bm's blocks are bstride complex elements apart (0: shared); Bm may alias X.
 // xs: workspace of n_omega * NB * T * solve_np(k) complex (FP64 size).
+// With g.P > 0 the superblock solve runs (rr_ssolve.hip; cbuf: n_omega * P *
+// T * solve_np(k) complex, FP64 size; flags: ssolve_counters() words), else
+// the tile-by-tile solve (rr_solve.hip).
 int solve_np(int k);
 hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
-                        double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
-                        int grid, hipStream_t s, const uint32_t* skip = nullptr);
+                        double* X, void* xs, void* cbuf, int* flags, uint32_t* ticket,
+                        uint32_t* status, int grid, hipStream_t s,
+                        const uint32_t* skip = nullptr);
+hipError_t launch_ssolve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
+                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
+                         double* X, void* xs, void* cbuf, int* cnt, uint32_t* ticket,
+                         uint32_t* status, int grid, hipStream_t s, const uint32_t* skip);
+int64_t ssolve_counters(const BandGeom& g, int n_omega);
+hipError_t prepare_ssolve(int T, bool fp32);
 
 // Small dense / tall-skinny kernels (rr_small.hip)
+constexpr int kJacobiSweeps = 40;  // one-sided Jacobi: sweeps before non-convergence
 struct SmallWs {   // workspace for tall-skinny reductions
   double* partial;     // n_omega * nchunk * kmax*kmax complex
   double* G;           // n_omega * kmax*kmax complex
@@ -147,10 +179,12 @@ struct SmallWs {   // workspace for tall-skinny reductions
   double* Rinv;        // n_omega * kmax*kmax complex (applied matrix)
   double* W;           // n_omega * kmax*kmax complex (SVD right vectors)
   double* Ut;          // n_omega * kmax*kmax complex (SVD left vectors)
-  double* rho;         // n_omega * 64: each column's last relative correction (refinement)
+  double* rho;         // n_omega * kRhoStride: each column's last relative correction
+                       // (refinement), then the measured contraction per direction
   uint32_t* shifted;   // n_omega: 1 where the first Cholesky QR pass needed the shift
   int nchunk;
   int kmax;
+  int jacobi_sweeps = kJacobiSweeps;  // sweep cap of the k x k Jacobi SVD
 };
 // CholQR2 in place: Y <- Q = Y R^-1 with R upper, real positive diagonal.
 // A shift whose Gram matrix is not numerically positive definite takes
@@ -195,12 +229,17 @@ hipError_t launch_gmres_finish(int64_t n, int n_omega, int k, const GmresWs& g, 
                                const uint32_t* skip, hipStream_t s);
 // X += D after correction `it` (0-based) and the per-column convergence test
 // on e_j = ||D_j|| / ||X_j||: converged when e_j <= tol or when the error left,
-// estimated as e_j times the contraction (e_j itself after the first
-// correction, e_j / e_j,prev after later ones), is below tol / 2.
+// estimated as e_j times the measured contraction of this shift and
+// direction (the ratio of successive corrections; rr_small.hip), is below
+// tol / 2.
+constexpr int kRhoStride = 64;  // doubles per shift in SmallWs::rho
+constexpr int kRhoSlot = 62;    // [62] forward, [63] adjoint: measured contraction
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D,
-                                double tol, int it, SmallWs& ws, uint32_t* status,
+                                double tol, int it, int adjoint, SmallWs& ws, uint32_t* status,
                                 uint32_t* fail_count, hipStream_t s,
                                 const uint32_t* skip = nullptr);
+// Zero the measured contractions of every shift (after a refactorisation).
+hipError_t launch_refine_reset(int n_omega, double* rho, hipStream_t s);
 // gradient kernel (rr_grad.hip)
 hipError_t launch_grad(int nx, int ny, double hx, double hy, int n_omega,
                        const double* omega, const double* sigma1, const double* u1,
@@ -239,6 +278,7 @@ struct rr_factors {
   size_t flag_count = 0;
   uint32_t* ctrl = nullptr;           // [0] status, [1] ticket, [2] refine fails
   void* xs = nullptr;                 // solve sweep workspace (row-major blocks)
+  void* cbuf = nullptr;               // superblock solve: c of the current superblock
   // vector workspaces (n_omega*k_max*n complex each unless noted)
   double* theta = nullptr;            // k_max*n (shared by all shifts)
   double* work1 = nullptr;
@@ -255,4 +295,7 @@ struct rr_factors {
   void* alloc_stream = nullptr;
   int refine_used = 0;
   bool sticky_hip_error = false;
+  // optional timing events (rr_set_timing_events): [0, 1] around the factor
+  // kernel, [2, 3] around the main solve launch of each solve call
+  hipEvent_t tev[4] = {nullptr, nullptr, nullptr, nullptr};
 };

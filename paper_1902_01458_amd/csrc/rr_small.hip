@@ -347,11 +347,15 @@ hipError_t launch_cholqr2(int n, int n_omega, int k, double* Y, SmallWs& ws, uin
 // R^H = Ut S J^H.  Pairs follow the round-robin (circle) order, k/2 disjoint
 // pairs per round, 8 threads per pair.  Outputs sorted by descending sigma.
 // Also forms Tv = Rinv * W for V = Z Tv.
+// A sweep that still rotated a pair after max_sweeps sweeps means the SVD has
+// not converged: ST_SVD_NOT_CONVERGED is latched (the results are returned
+// as they stand).
 __global__ __launch_bounds__(256) void k_jacobi_svd(int k, int kmax, const double2* __restrict__ Rg,
                                                     const double2* __restrict__ Rinvg,
                                                     double* __restrict__ sigma,
                                                     double2* __restrict__ Utg, double2* __restrict__ Wg,
-                                                    double2* __restrict__ Tvg, uint32_t* status) {
+                                                    double2* __restrict__ Tvg, uint32_t* status,
+                                                    int max_sweeps) {
   __shared__ double2 A[KM][KM + 1];  // A[row][col]
   __shared__ double2 J[KM][KM + 1];
   __shared__ double sv[KM];
@@ -370,7 +374,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(int k, int kmax, const doubl
   __syncthreads();
   const int npair = m / 2;
   const int pair = threadIdx.x >> 3, sub = threadIdx.x & 7;
-  for (int sweep = 0; sweep < 40; sweep++) {
+  for (int sweep = 0; sweep < max_sweeps; sweep++) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int rnd = 0; rnd < m - 1; rnd++) {
@@ -421,6 +425,9 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(int k, int kmax, const doubl
     if (!rotated) break;
     __syncthreads();
   }
+  // every thread read `rotated` after the last round's barrier; nothing has
+  // written it since
+  if (threadIdx.x == 0 && rotated) latch(status, ST_SVD_NOT_CONVERGED);
   for (int c = threadIdx.x; c < k; c += 256) {
     double s = 0;
     for (int a = 0; a < k; a++) s += A[a][c].x * A[a][c].x + A[a][c].y * A[a][c].y;
@@ -470,7 +477,7 @@ hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const do
   // W and its product with R^-1 (ws.G holds Tv = R^-1 W)
   hipLaunchKernelGGL(k_jacobi_svd, dim3(n_omega), dim3(256), 0, s, k, ws.kmax,
                      (const double2*)ws.R, (const double2*)ws.Rinv, sigma, (double2*)ws.Ut,
-                     (double2*)ws.W, (double2*)ws.G, status);
+                     (double2*)ws.W, (double2*)ws.G, status, ws.jacobi_sweeps);
   // V = Z R^-1 W = Qz W
   hipLaunchKernelGGL(k_apply_small, dim3((n + 255) / 256, n_omega), dim3(256), 0, s,
                      (int64_t)n, k, (const double2*)Z, (const double2*)ws.G, ws.kmax, (double2*)V,
@@ -571,35 +578,77 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
   return hipGetLastError();
 }
 
-// After X += D: a column has converged when ||D_j|| <= tol ||X_j||.  Counts
-// unconverged columns into *fail_count (reset by the caller per solve).
+// After X += D, per column j: e_j = ||D_j|| / ||X_j||, the size of the
+// correction just applied.  Refinement shrinks the error by a contraction
+// rho = ||I - M32^-1 M|| (per shift and direction) per correction, so the
+// error left is about rho e_j.  rho is never assumed: it is measured as the
+// ratio of two successive corrections, e_j / e_j,prev, and kept per shift
+// and direction as the largest ratio seen since the factorisation (slot
+// kRhoSlot + adjoint of the shift's row; zero = not measured yet).  A column
+// has converged when e_j <= tol, or when the error it leaves, estimated with
+// rho (this solve's own ratio from the second correction on, else the one
+// kept from earlier solves), is at most tol / 2.  So the first solve in each
+// direction after a factorisation takes a second correction unless the
+// first already meets tol, and later ones stop after one when the measured
+// contraction allows it.  Unconverged columns are counted into *fail_count
+// (reset by the caller per correction).
 __global__ void k_refine_check(int k, int nchunk, const double* px, const double* pd, double tol,
-                               int it, double* rho, uint32_t* fail_count, uint32_t* status,
-                               const uint32_t* skip) {
+                               int it, int adjoint, double* rho, uint32_t* fail_count,
+                               uint32_t* status, const uint32_t* skip) {
   if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  __shared__ double ratio_max;
   const int w = blockIdx.x;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+  double* rw = rho + (int64_t)w * kRhoStride;
+  double e = 0.0, ratio = 0.0;
+  const int j = threadIdx.x;
+  if (threadIdx.x == 0) ratio_max = 0.0;
+  __syncthreads();
+  if (j < k) {
     double sx = 0, sd = 0;
     for (int c = 0; c < nchunk; c++) {
       sx += px[((int64_t)w * nchunk + c) * 64 + j];
       sd += pd[((int64_t)w * nchunk + c) * 64 + j];
     }
     if (!isfinite(sx) || !isfinite(sd)) latch(status, ST_NONFINITE);
-    // relative correction e and contraction estimate (refinement shrinks the
-    // error by about the same factor per correction; the first correction
-    // measures that factor as the error of the first solve)
-    const double e = sx > 0 ? sqrt(sd / sx) : (sd > 0 ? INFINITY : 0.0);
-    double* prev = rho + (int64_t)w * 64 + j;
-    const double contraction = it == 0 ? e : (*prev > 0 ? e / *prev : INFINITY);
-    *prev = e;
-    const bool ok = e <= tol || 2.0 * e * contraction <= tol;
+    e = sx > 0 ? sqrt(sd / sx) : (sd > 0 ? INFINITY : 0.0);
+    if (it > 0) {
+      const double prev = rw[j];
+      ratio = prev > 0 ? e / prev : (e > 0 ? INFINITY : 0.0);
+      // doubles compare as their bit patterns when non-negative
+      atomicMax(reinterpret_cast<unsigned long long*>(&ratio_max),
+                (unsigned long long)__double_as_longlong(ratio));
+    }
+  }
+  __syncthreads();
+  double* kept = rw + kRhoSlot + (adjoint ? 1 : 0);
+  const double rho_kept = *kept;
+  if (j < k) {
+    rw[j] = e;
+    const double r = it > 0 ? fmax(ratio, rho_kept) : rho_kept;
+    const bool ok = e <= tol || (r > 0.0 && 2.0 * e * r <= tol);
     if (!ok) atomicAdd(fail_count, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && it > 0) *kept = fmax(rho_kept, ratio_max);
+}
+
+// Forget the measured contractions (a new factorisation).
+__global__ void k_refine_reset(int n_omega, double* rho) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < n_omega) {
+    rho[(int64_t)w * kRhoStride + kRhoSlot] = 0.0;
+    rho[(int64_t)w * kRhoStride + kRhoSlot + 1] = 0.0;
   }
 }
 
+hipError_t launch_refine_reset(int n_omega, double* rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_reset, dim3((n_omega + 255) / 256), dim3(256), 0, s, n_omega, rho);
+  return hipGetLastError();
+}
+
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D, double tol,
-                                int it, SmallWs& ws, uint32_t* status, uint32_t* fail_count,
-                                hipStream_t s, const uint32_t* skip) {
+                                int it, int adjoint, SmallWs& ws, uint32_t* status,
+                                uint32_t* fail_count, hipStream_t s, const uint32_t* skip) {
   int nc = nchunks(n);
   if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
   double* px = ws.partial;
@@ -607,7 +656,7 @@ hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const doub
   hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
                      (double2*)X, (const double2*)D, nc, px, pd, skip);
   hipLaunchKernelGGL(k_refine_check, dim3(n_omega), dim3(64), 0, s, k, nc, px, pd, tol, it,
-                     ws.rho, fail_count, status, skip);
+                     adjoint, ws.rho, fail_count, status, skip);
   return hipGetLastError();
 }
 

@@ -150,15 +150,18 @@ __global__ __launch_bounds__(64 * (T / 16) * (NP / 16), 2) void k_solve2(Solve2P
   extern __shared__ __align__(16) char solve_smem[];
   cplx<R>* blk = reinterpret_cast<cplx<R>*>(solve_smem);  // pre-diagonal block, row-major
   cplx<R>* gl = blk + T * NP;  // copies of the chain tiles d = 1 .. kChainLds (T*T each)
-  // the ticket broadcast word shares the staging block (free when a ticket is
-  // taken), so that the FP64 layout fits the 160 KiB of LDS exactly
-  uint32_t* s_ticket = reinterpret_cast<uint32_t*>(solve_smem);
+  // The ticket broadcast word has LDS of its own.  It must not share the
+  // staging block: a task with no far blocks reaches the store into blk[0]
+  // with no barrier after the ticket read, so a wave still reading the
+  // ticket could see the stored value instead, skip its task and leave the
+  // task's flag unpublished.
+  __shared__ uint32_t s_ticket;
   typedef typename Mf<R>::v4 v4;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rb = wave / NCB, cb = wave % NCB;
   const int B = P.g.B, NB = P.g.NB, RT = P.g.row_tiles();
   for (;;) {
-    const int64_t ticket = wg_ticket(P.ticket, s_ticket);
+    const int64_t ticket = wg_ticket(P.ticket, &s_ticket);
     if (ticket >= P.total) break;
     // (shift, column group) pairs are independent chains of the same factor
     const int nv = P.n_omega * P.ngroups;
@@ -329,8 +332,9 @@ static hipError_t prepare_t() {
 // Dynamic-LDS limits of the solve kernels of one tile / precision (host
 // calls, kept out of the launch path so that launches can be captured).
 hipError_t prepare_solve(int T, bool fp32) {
-  if (fp32) return T == 64 ? prepare_t<float, 64>() : prepare_t<float, 32>();
-  return T == 64 ? prepare_t<double, 64>() : prepare_t<double, 32>();
+  hipError_t e = fp32 ? (T == 64 ? prepare_t<float, 64>() : prepare_t<float, 32>())
+                      : (T == 64 ? prepare_t<double, 64>() : prepare_t<double, 32>());
+  return e == hipSuccess ? prepare_ssolve(T, fp32) : e;
 }
 
 template <typename R, int T, int NP>
@@ -348,8 +352,11 @@ int solve_np(int k) { return ((k + 15) / 16) * 16; }
 
 hipError_t launch_solve(const BandGeom& g, int n, int n_omega, int k, bool fp32,
                         const void* tiles, int adjoint, const double* Bm, int64_t bstride,
-                        double* X, void* xs, int* flags, uint32_t* ticket, uint32_t* status,
-                        int grid, hipStream_t s, const uint32_t* skip) {
+                        double* X, void* xs, void* cbuf, int* flags, uint32_t* ticket,
+                        uint32_t* status, int grid, hipStream_t s, const uint32_t* skip) {
+  if (g.P > 0)
+    return launch_ssolve(g, n, n_omega, k, fp32, tiles, adjoint, Bm, bstride, X, xs, cbuf, flags,
+                         ticket, status, grid, s, skip);
   // The right-hand sides are split into groups of 16 columns, each an
   // independent chain: half the MFMA work per block step on the chain for
   // k in (16, 32], and twice the chains in flight.

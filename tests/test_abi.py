@@ -64,6 +64,7 @@ def test_invalid_arguments_rejected_on_host():
     assert L.rr_gains(None, 4, None, None, 0, None, None, None, None, None) == 1
     assert L.rr_resvd(None, 4, None, None, None, None, None, None, None) == 1
     assert L.rr_set_test_matrix(None, 0, 0) == 1
+    assert L.rr_set_jacobi_sweeps(None, 40) == 1
     assert L.rr_sketch(None, 4, 0, 0, 0, None, None) == 1
     assert L.rr_grad(None, None, None, None, 0, None, None, None, None) == 1
     assert L.rr_check(None, None) == 1
@@ -106,7 +107,9 @@ def test_factor_bytes_matches_the_layout():
     nx, ny, nw, k, T = 512, 256, 16, 20, 64
     n, b = 2 * nx * ny, 2 * ny
     B, NB = -(-b // T), -(-n // T)
-    tiles = nw * NB * (2 * B + 1 + 13) * T * T * 16  # band, chain and LU tiles, complex FP64
+    P = min(B, 256 // T)  # the default superblock: 4 block rows of 64
+    # the band, the block-inverse LU and P - 1 superblock-inverse tiles per row, complex FP64
+    tiles = nw * NB * (2 * B + 1 + 1 + (P - 1)) * T * T * 16
     got = L.rr_factor_bytes(nx, ny, nw, k, 0, T)
     assert tiles < got < tiles * 1.2
     # FP32 factor: half the tile bytes, one more vector workspace

@@ -58,3 +58,27 @@ def test_more_shifts_than_one_factor_launch():
         assert gain_errors(to_np(out["sigma_B"])[i], ref.sigma_B).max() <= 1e-10, i
         assert gain_errors(to_np(out["sigma_AV"])[i], ref.sigma_AV).max() <= 1e-10, i
     out["factors"].free()
+
+
+def test_jacobi_svd_reports_non_convergence():
+    """With the Jacobi SVD capped at one sweep, a k x k factor that is not
+    already diagonal still rotates at the cap: rr_check reports
+    RR_ERR_NOT_CONVERGED instead of returning unconverged gains silently;
+    the default cap on the same handle converges and matches the oracle."""
+    w = W.small("j", 12, 8, nu=2e-2, omegas=(0.9,), k=12)
+    prob = rr().BurgersProblem.from_workload(w)
+    f = rr().factor(prob, list(w.omegas), "fp64", k_max=w.k, tile=32)
+    Q = f.sketch_solve(w.k, w.seed, 0)
+    Z = f.adjoint_solve(Q)
+    f.set_jacobi_sweeps(1)
+    f.gains(Q, Z, "av")
+    with pytest.raises(rr().RRError) as e:
+        f.check()
+    assert e.value.status == 3 and "Jacobi" in str(e.value)
+    f.set_jacobi_sweeps(40)
+    out = f.gains(Q, Z, "av")
+    f.check()
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    ref = ores.randomized_resolvent(L, 0.9, osk.test_matrix(w.n, w.k, phi, w.seed), q=0)
+    assert gain_errors(to_np(out["sigma_B"])[0], ref.sigma_B).max() <= 1e-10
+    f.free()

@@ -176,7 +176,7 @@ def test_gradient_matches_oracle_formula():
     for i in range(len(w.omegas)):
         u = to_np(out["U"][i, 0])
         v = to_np(out["V"][i, 0])
-        g, gnu, gom = ograd.gradient(float(s1[i]), u, v, w.nx, w.ny, hx, hy)
+        g, gnu, gom = ograd.gradient_full(float(s1[i]), u, v, w.nx, w.ny, hx, hy)
         np.testing.assert_allclose(to_np(dU[i]), g, rtol=0, atol=1e-12 * np.abs(g).max())
         assert abs(float(dnu[i]) - gnu) <= 1e-12 * abs(gnu)
         assert abs(float(dom[i]) - gom) <= 1e-12 * max(abs(gom), float(s1[i]))
@@ -221,3 +221,42 @@ def test_refactor_is_bitwise_repeatable(prec):
         R = Bm - prob.apply(list(w.omegas), X0)
         rel = (torch.linalg.vector_norm(R, dim=2) / torch.linalg.vector_norm(Bm, dim=2)).max()
         assert float(rel) < 1e-12
+
+
+SUPERBLOCK_CASES = [  # (nx, ny, tile, k, superblock): B tiles per half-band against P
+    (16, 96, 32, 12, 1),    # B = 6, one block row per step (diagonal inverses only)
+    (16, 96, 32, 12, 3),    # B = 6, ragged superblocks (NB = 96 = 32 x 3)
+    (13, 70, 32, 20, 8),    # B = 5 < P: the superblock spans more than the half-band
+    (12, 100, 64, 32, 4),   # B = 4 = P, ragged n, k = 32
+    (9, 48, 64, 17, 2),     # B = 2 = P, NB odd
+    (10, 6, 32, 3, 5),      # B = 1, a partial last superblock
+    (24, 40, 32, 5, -1),    # the tile-by-tile solve with chain tiles
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nx,ny,tile,k,sb", SUPERBLOCK_CASES)
+def test_superblock_solve_matches_oracle(prec, nx, ny, tile, k, sb):
+    """Forward and adjoint solves with every superblock size against LAPACK's
+    banded solve (zgbtrs), FP64 (1e-11) and FP32 without refinement
+    corrections (a 1e-4 bound on the normwise error: an FP32 LU, kappa ~ 1e2)."""
+    w = W.small("sb", nx, ny, nu=2e-2)
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    prob = rr().BurgersProblem.from_workload(w)
+    oms = [0.4, 2.5, 1.1]
+    f = rr().factor(prob, oms, prec, k_max=k, tile=tile, superblock=sb, refine_tol=1.0)
+    rng = np.random.Generator(np.random.PCG64(12))
+    Bm = rng.standard_normal((3, k, w.n)) + 1j * rng.standard_normal((3, k, w.n))
+    Bt = torch.tensor(Bm, device="cuda")
+    X = to_np(f.solve(Bt))
+    Z = to_np(f.adjoint_solve(Bt))
+    f.check()
+    tol = 1e-11 if prec == "fp64" else 1e-4
+    for i, om in enumerate(oms):
+        S = ShiftedSolver(op.shifted(L, om), "gb")
+        ref = S.solve(Bm[i].T).T
+        refh = S.solve_adjoint(Bm[i].T).T
+        ex = np.linalg.norm(X[i] - ref) / np.linalg.norm(ref)
+        ez = np.linalg.norm(Z[i] - refh) / np.linalg.norm(refh)
+        assert ex <= tol and ez <= tol, (i, ex, ez)
+    f.free()
