@@ -279,6 +279,24 @@ rr_status rr_resvd(rr_factors* f, int32_t k, const double* Us, const double* sca
 rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const double* v1,
                   int64_t vec_stride, double* dU, double* dnu, double* domega, void* stream);
 
+/* rr_grad for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same gradient, by the same kernels, without a handle.  The problem gives
+ * the grid and domain (p->nx, p->ny, p->x0..y1; coef, phi, U and nu are not
+ * read); sigma1, u1, v1, vec_stride, dU, dnu, domega are as for rr_grad, for
+ * n_omega shifts.  The kernels' partial sums live in a file-scope device
+ * array of 2^18 doubles (2 MiB) per GPU, held until the process ends, so
+ * 2 * n_omega * ceil((nx+2)(ny+2) / 256) may not exceed 2^18 (RR_ERR_INVALID
+ * otherwise, before anything is launched; e.g. 63 shifts at 1024 x 512).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from several threads) race and must be ordered
+ * by the caller.  The first call on a device looks the array up
+ * (hipGetSymbolAddress, no allocation); every call then only reads the
+ * current device and launches the two kernels. */
+rr_status rr_grad_noalloc(const rr_problem* p, int32_t n_omega, const double* sigma1,
+                          const double* u1, const double* v1, int64_t vec_stride, double* dU,
+                          double* dnu, double* domega, void* stream);
+
 /* Synchronise `stream` and return (then clear) the first device-side error
  * latched in the handle since the last check; RR_OK if none. */
 rr_status rr_check(rr_factors* f, void* stream);

@@ -22,7 +22,7 @@ EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sket
            "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
            "rr_sketch", "rr_factor_schedule", "rr_set_test_matrix", "rr_set_jacobi_sweeps",
-           "rr_set_timing_events")
+           "rr_grad_noalloc", "rr_set_timing_events")
 
 
 class RRError(RuntimeError):
@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
         "rr_gains": [vp, i32, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp],
         "rr_resvd": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
         "rr_grad": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
+        "rr_grad_noalloc": [pp, i32, vp, vp, vp, i64, vp, vp, vp, vp],
         "rr_check": [vp, vp],
         "rr_refine_count": [vp],
         "rr_bytes": [vp],

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "rr_internal.h"
@@ -563,6 +564,67 @@ rr_status rr_grad(rr_factors* f, const double* sigma1, const double* u1, const d
   if (vec_stride < f->n && f->n_omega > 1) return fail(RR_ERR_INVALID, "vec_stride < n");
   RR_HIP(launch_grad(f->nx, f->ny, f->hx, f->hy, f->n_omega, f->omega, sigma1, u1, v1, vec_stride,
                      dU, dnu, domega, f->grad_partial, f->grad_nchunk, (hipStream_t)stream));
+  return RR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient without allocation: the partial sums of k_grad go to a file-scope
+// device array instead of a handle's workspace.  Each GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device
+// (the array's name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+constexpr int64_t kGradScratchDoubles = int64_t(1) << 18;  // 2 MiB per GPU
+static __device__ __align__(256) double scratch[kGradScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// This device's copy of `scratch`, looked up once per device (with that
+// device current) and kept.
+rr_status scratch_for_current_device(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(RR_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RR_ERR_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return RR_OK;
+}
+}  // namespace
+
+rr_status rr_grad_noalloc(const rr_problem* p, int32_t n_omega, const double* sigma1,
+                          const double* u1, const double* v1, int64_t vec_stride, double* dU,
+                          double* dnu, double* domega, void* stream) {
+  if (!p || !sigma1 || !u1 || !v1 || !dU || !dnu || !domega)
+    return fail(RR_ERR_INVALID, "NULL pointer");
+  if (p->nx < 1 || p->ny < 1 || n_omega < 1 || n_omega > 65535)
+    return fail(RR_ERR_INVALID, "bad sizes");
+  if (!(p->x1 > p->x0) || !(p->y1 > p->y0)) return fail(RR_ERR_INVALID, "empty domain");
+  const int64_t n = 2 * (int64_t)p->nx * p->ny;
+  if (vec_stride < n && n_omega > 1) return fail(RR_ERR_INVALID, "vec_stride < n");
+  const int64_t nfull = (int64_t)(p->nx + 2) * (p->ny + 2);
+  const int64_t nchunk = (nfull + 255) / 256;  // k_grad's blocks per shift
+  const int64_t need = 2 * nchunk * n_omega;
+  if (need > kGradScratchDoubles)
+    return fail(RR_ERR_INVALID, "rr_grad_noalloc needs " + std::to_string(need) +
+                                    " doubles of scratch; the maximum is " +
+                                    std::to_string(kGradScratchDoubles));
+  double* ws = nullptr;
+  rr_status st = scratch_for_current_device(&ws);
+  if (st != RR_OK) return st;
+  const double hx = (p->x1 - p->x0) / (p->nx + 1), hy = (p->y1 - p->y0) / (p->ny + 1);
+  RR_HIP(launch_grad(p->nx, p->ny, hx, hy, n_omega, nullptr, sigma1, u1, v1, vec_stride, dU,
+                     dnu, domega, ws, (int)nchunk, (hipStream_t)stream));
   return RR_OK;
 }
 
