@@ -63,11 +63,12 @@ def run_path(prob, w, precision, steps, warmup, tile, refine_iters, autotune, gr
     import torch
 
     import paper_1902_01458_amd as rr
-    tune = {"tile": tile, "grid": 0, "ms": None}
+    tune = {"tile": tile, "grid": 0, "superblock": 0, "ms": None}
     if autotune:
         tune = rr.autotune(prob, list(w.omegas), w.k, precision)
     f = rr.factor(prob, list(w.omegas), precision, k_max=w.k, tile=tune["tile"],
-                  grid=tune["grid"], refine_iters=refine_iters, refine_tol=refine_tol)
+                  grid=tune["grid"], superblock=tune["superblock"], refine_iters=refine_iters,
+                  refine_tol=refine_tol)
     f.check()
     stream = torch.cuda.current_stream()
     Q = f.empty_block(w.k)
@@ -350,11 +351,13 @@ def main():
         byt = n_om * (w.n * (2 * b + 1) * esize + 2 * w.k * w.n * 16)
         bw = byt / (res["solve_ms"] * 1e-3) / 1e9
         np_ = 16 * ((w.k + 15) // 16)
+        T = res["tune"]["tile"]
+        kname = (f"k_solve2<{name},{T},16,false>" if (res["tune"].get("superblock") or 0) < 0
+                 else f"k_ssolve<{name},{T},{np_},false>")
         return {"bound": "hbm", "achieved": bw, "peak": 8000.0, "unit": "GB/s",
-                "frac": bw / 8000.0, "bytes_per_launch": byt,
-                "traffic": traffic(f"k_ssolve<{name},{res['tune']['tile']},{np_},false>"),
-                "kernel": f"k_ssolve<{name},{res['tune']['tile']},{np_},false> (forward solve of "
-                          f"the eq. 9 recovery, all {n_om} shifts x {w.k} columns, one launch)",
+                "frac": bw / 8000.0, "bytes_per_launch": byt, "traffic": traffic(kname),
+                "kernel": f"{kname} (forward solve of the eq. 9 recovery, all {n_om} shifts x "
+                          f"{w.k} columns, one launch)",
                 "launch_ms": res["solve_ms"]}
     line = {
         "metric": METRIC, "value": value, "unit": "ω-solves/s", "n_gpus": 1,
@@ -365,6 +368,7 @@ def main():
                                f"half-bandwidth {b}, {n_om} shifts 0.25..8, k={w.k}, q={w.q}, "
                                "Phi-weighted Gaussian sketch, seed 0",
                    "tile": mixed["tune"]["tile"], "grid": mixed["tune"]["grid"],
+                   "superblock": mixed["tune"].get("superblock"),
                    "autotuned": auto, "refine_tol": args.refine_tol, "refine_tol_sketch": 1e-8},
         "gains_per_s": value * w.k,
         "sigma1_rel_err_vs_oracle": accuracy(mixed, gold),
@@ -385,6 +389,7 @@ def main():
                         "optional_svd_ms": fp64["optional_svd_ms"],
                         "graph_ms_per_step": fp64.get("graph_ms_per_step"),
                         "tile": fp64["tune"]["tile"], "grid": fp64["tune"]["grid"],
+                        "superblock": fp64["tune"].get("superblock"),
                         "sigma1_rel_err_vs_oracle": accuracy(fp64, gold),
                         "factor_roofline": {"bound": "mfma", "achieved": a64,
                                             "peak": PEAK["fp64"], "unit": "TFLOP/s",

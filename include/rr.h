@@ -367,16 +367,23 @@ rr_status rr_graph_capture(rr_factors* f, int32_t refactor, int32_t k, uint64_t 
 rr_status rr_graph_launch(rr_graph* g, void* stream);
 void rr_graph_free(rr_graph* g);
 
-/* Autotuner for the band tile and the persistent grid: for each candidate
- * (tile 64 or 32, one or two workgroups per CU) it builds a trial handle for
- * this operator and the first max_shifts shifts (all when max_shifts <= 0),
- * runs one warm-up pass and one timed pass of refactorisation, sketch solve
- * and adjoint solve, and scores factor + 2.5 * (sketch + adjoint), the cost
- * of one pass of Algorithm 1 with a subspace iteration.  The fastest
- * candidate is written to *out (refinement fields zero: defaults) and its
- * score in ms to *out_ms (may be NULL).  Candidates that do not fit in device
- * memory are skipped.  Synchronises `stream`; allocates and frees its own
- * trial handles and blocks; the caller's handles are untouched. */
+/* Autotuner for the band tile, the persistent grid and the solve's
+ * superblock: it first tries tile 64 and 32 with one and two workgroups per
+ * CU (default superblock), then, for the best of those, superblocks of 2, 4
+ * and 8 block rows and the tile-by-tile solve; each candidate builds a trial
+ * handle for this operator and the first max_shifts shifts (all when
+ * max_shifts <= 0), runs one warm-up pass and one timed pass of
+ * refactorisation, sketch solve and adjoint solve, and is scored factor +
+ * 2.5 * (sketch + adjoint), the cost of one pass of Algorithm 1 with a
+ * subspace iteration.  The fastest candidate is written to *out (refinement
+ * fields zero: defaults) and its score in ms to *out_ms (may be NULL).
+ * Candidates that do not fit in device memory are skipped.  When the
+ * environment variable RR_AUTOTUNE_CACHE names a file, picks are kept there
+ * (a JSON object keyed by GPU architecture, grid, shift count, k and
+ * precision): a key already in it is returned with its stored score and no
+ * trial runs; a new pick is added.  Synchronises `stream`; allocates and
+ * frees its own trial handles and blocks; the caller's handles are
+ * untouched. */
 rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double* omega_im,
                       int32_t n_omega, int32_t k, rr_precision prec, int32_t max_shifts,
                       void* stream, rr_tuning* out, double* out_ms);

@@ -355,8 +355,9 @@ def factor_bytes(nx: int, ny: int, n_omega: int, k_max: int, precision: str = "f
 
 def autotune(prob: BurgersProblem, omegas, k: int, precision: str = "fp64",
              max_shifts: int = 0, stream=None) -> dict:
-    """The library's autotuner (rr_autotune): fastest band tile and persistent
-    grid for this operator, shift batch, width and precision."""
+    """The library's autotuner (rr_autotune): fastest band tile, persistent
+    grid and solve superblock for this operator, shift batch, width and
+    precision (cached in the file RR_AUTOTUNE_CACHE names, if set)."""
     om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
     re = np.ascontiguousarray(om.real)
     im = np.ascontiguousarray(om.imag)
@@ -367,11 +368,11 @@ def autotune(prob: BurgersProblem, omegas, k: int, precision: str = "fp64",
                             im.ctypes.data_as(ctypes.c_void_p), om.size, k,
                             PRECISIONS[precision], max_shifts, ctypes.c_void_p(_stream(stream)),
                             ctypes.byref(t), ctypes.byref(ms)))
-    return {"tile": t.tile, "grid": t.grid, "ms": ms.value}
+    return {"tile": t.tile, "grid": t.grid, "superblock": t.superblock, "ms": ms.value}
 
 
-def _sweep_chunk(prob, om, k, seed, q, precision, tile, grid):
-    f = factor(prob, om, precision, k_max=k, tile=tile, grid=grid)
+def _sweep_chunk(prob, om, k, seed, q, precision, tile, grid, superblock=0):
+    f = factor(prob, om, precision, k_max=k, tile=tile, grid=grid, superblock=superblock)
     g = None
     try:
         g = capture(f, k, seed, q, "av", refactor=False)
@@ -405,6 +406,7 @@ def sweep(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
     om = np.asarray(omegas, dtype=np.complex128).reshape(-1)
     tile = int(tune["tile"]) if tune else 0
     grid = int(tune["grid"]) if tune else 0
+    sb = int(tune.get("superblock", 0)) if tune else 0
     if chunk <= 0:
         chunk = _chunk_size(prob, k, precision, tile, memory_fraction, om.size)
     sB = torch.empty((om.size, k), dtype=torch.float64, device="cuda")
@@ -414,7 +416,7 @@ def sweep(prob: BurgersProblem, omegas, k: int, q: int = 0, seed: int = 0,
         c1 = min(om.size, c0 + chunk)
         try:
             sB[c0:c1], sAV[c0:c1] = _sweep_chunk(prob, om[c0:c1], k, seed, q, precision, tile,
-                                                 grid)
+                                                 grid, sb)
         except RRError as e:
             if on_failure != "fp64" or precision != "mixed" or e.status not in _FP64_CURABLE:
                 raise

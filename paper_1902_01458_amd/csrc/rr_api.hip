@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -777,6 +778,87 @@ rr_status rr_graph_launch(rr_graph* g, void* stream) {
 // ---------------------------------------------------------------------------
 // Autotuner
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// Cache of autotuner picks: a JSON object, one entry per line,
+//   "gfx950|512x256|w16|k20|mixed": {"tile": 64, "grid": 512, "superblock": 4, "ms": 812.5},
+// at the path named by RR_AUTOTUNE_CACHE (no cache when unset).
+std::string tune_key(const rr_problem* p, int nw, int k, rr_precision prec) {
+  std::string arch = "gpu";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+  } else {
+    (void)hipGetLastError();
+  }
+  return arch + "|" + std::to_string(p->nx) + "x" + std::to_string(p->ny) + "|w" +
+         std::to_string(nw) + "|k" + std::to_string(k) + "|" + (prec == RR_MIXED ? "mixed" : "fp64");
+}
+
+std::vector<std::string> cache_lines(const char* path) {
+  std::vector<std::string> out;
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return out;
+  char buf[1024];
+  while (std::fgets(buf, sizeof(buf), fh)) {
+    std::string ln(buf);
+    if (ln.find("\": {") != std::string::npos) {
+      while (!ln.empty() && (ln.back() == '\n' || ln.back() == ',' || ln.back() == '\r'))
+        ln.pop_back();
+      out.push_back(ln);
+    }
+  }
+  std::fclose(fh);
+  return out;
+}
+
+bool cache_lookup(const char* path, const std::string& key, rr_tuning* t, double* ms) {
+  for (const std::string& ln : cache_lines(path)) {
+    if (ln.compare(0, key.size() + 2, "\"" + key + "\"") != 0) continue;
+    const size_t o = ln.find('{');
+    int tile = 0, grid = 0, sb = 0;
+    double v = 0;
+    if (std::sscanf(ln.c_str() + o, "{\"tile\": %d, \"grid\": %d, \"superblock\": %d, \"ms\": %lf}",
+                    &tile, &grid, &sb, &v) == 4) {
+      *t = rr_tuning{};
+      t->tile = tile;
+      t->grid = grid;
+      t->superblock = sb;
+      *ms = v;
+      return true;
+    }
+  }
+  return false;
+}
+
+void cache_store(const char* path, const std::string& key, const rr_tuning& t, double ms) {
+  std::vector<std::string> lines;
+  for (const std::string& ln : cache_lines(path))
+    if (ln.compare(0, key.size() + 2, "\"" + key + "\"") != 0) lines.push_back(ln);
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "\"%s\": {\"tile\": %d, \"grid\": %d, \"superblock\": %d, \"ms\": %.17g}",
+                key.c_str(), t.tile, t.grid, t.superblock, ms);
+  lines.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fh = std::fopen(tmp.c_str(), "w");
+  if (!fh) return;
+  std::fprintf(fh, "{\n");
+  for (size_t i = 0; i < lines.size(); i++)
+    std::fprintf(fh, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+  std::fprintf(fh, "}\n");
+  std::fclose(fh);
+  (void)std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" {
+
 rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double* omega_im,
                       int32_t n_omega, int32_t k, rr_precision prec, int32_t max_shifts,
                       void* stream, rr_tuning* out, double* out_ms) {
@@ -785,11 +867,16 @@ rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double*
   const int nw = (max_shifts > 0 && max_shifts < n_omega) ? max_shifts : n_omega;
   const int64_t n = 2 * (int64_t)p->nx * p->ny;
   hipStream_t s = (hipStream_t)stream;
+  const char* cache = std::getenv("RR_AUTOTUNE_CACHE");
+  const std::string key = tune_key(p, nw, k, prec);
+  if (cache && *cache) {
+    double ms = 0;
+    if (cache_lookup(cache, key, out, &ms)) {
+      if (out_ms) *out_ms = ms;
+      return RR_OK;
+    }
+  }
   const int cus = device_cus();
-  const int tiles[2] = {64, 32};
-  const int grids[2] = {cus, 2 * cus};
-  double best = -1.0;
-  rr_tuning pick{};
   double *Q = nullptr, *Z = nullptr;
   const size_t vb = (size_t)nw * k * n * 2 * sizeof(double);
   if (hipMalloc((void**)&Q, vb) != hipSuccess || hipMalloc((void**)&Z, vb) != hipSuccess) {
@@ -799,39 +886,68 @@ rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double*
   }
   hipEvent_t ev[4];
   for (auto& x : ev) (void)hipEventCreate(&x);
-  rr_status st = RR_OK;
-  for (int ti = 0; ti < 2 && st == RR_OK; ti++) {
-    for (int gi = 0; gi < 2 && st == RR_OK; gi++) {
-      rr_tuning t{tiles[ti], grids[gi], 0, 0.0, 0.0};
-      rr_factors* h = nullptr;
-      rr_status fs = rr_factor(p, omega_re, omega_im, nw, k, prec, &t, stream, &h);
-      if (fs == RR_ERR_NOMEM) continue;  // this candidate does not fit
-      if (fs != RR_OK) { st = fs; break; }
-      // warm-up pass, then one timed pass: factor, sketch solve, adjoint solve
-      fs = rr_sketch_solve(h, k, 0, 0, Q, stream);
+  // one trial: factor, sketch solve and adjoint solve of the first nw shifts;
+  // score = factor + 2.5 (sketch + adjoint), one pass of Algorithm 1 with a
+  // subspace iteration; < 0 when the candidate does not fit in memory
+  auto trial = [&](const rr_tuning& t, double* score) -> rr_status {
+    *score = -1.0;
+    rr_factors* h = nullptr;
+    rr_status fs = rr_factor(p, omega_re, omega_im, nw, k, prec, &t, stream, &h);
+    if (fs == RR_ERR_NOMEM) return RR_OK;
+    if (fs != RR_OK) return fs;
+    fs = rr_sketch_solve(h, k, 0, 0, Q, stream);  // warm-up pass
+    if (fs == RR_OK) fs = rr_adjoint_solve(h, k, Q, Z, stream);
+    if (fs == RR_OK) fs = rr_check(h, stream);
+    float ms_f = 0, ms_s = 0, ms_a = 0;
+    if (fs == RR_OK) {
+      (void)hipEventRecord(ev[0], s);
+      fs = rr_refactor(h, stream);
+      (void)hipEventRecord(ev[1], s);
+      if (fs == RR_OK) fs = rr_sketch_solve(h, k, 0, 0, Q, stream);
+      (void)hipEventRecord(ev[2], s);
       if (fs == RR_OK) fs = rr_adjoint_solve(h, k, Q, Z, stream);
+      (void)hipEventRecord(ev[3], s);
       if (fs == RR_OK) fs = rr_check(h, stream);
-      float ms_f = 0, ms_s = 0, ms_a = 0;
-      if (fs == RR_OK) {
-        (void)hipEventRecord(ev[0], s);
-        fs = rr_refactor(h, stream);
-        (void)hipEventRecord(ev[1], s);
-        if (fs == RR_OK) fs = rr_sketch_solve(h, k, 0, 0, Q, stream);
-        (void)hipEventRecord(ev[2], s);
-        if (fs == RR_OK) fs = rr_adjoint_solve(h, k, Q, Z, stream);
-        (void)hipEventRecord(ev[3], s);
-        if (fs == RR_OK) fs = rr_check(h, stream);
-        (void)hipEventElapsedTime(&ms_f, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&ms_s, ev[1], ev[2]);
-        (void)hipEventElapsedTime(&ms_a, ev[2], ev[3]);
+      (void)hipEventElapsedTime(&ms_f, ev[0], ev[1]);
+      (void)hipEventElapsedTime(&ms_s, ev[1], ev[2]);
+      (void)hipEventElapsedTime(&ms_a, ev[2], ev[3]);
+    }
+    rr_factors_free(h);
+    if (fs == RR_OK) *score = ms_f + 2.5 * (ms_s + ms_a);
+    return fs;
+  };
+  rr_status st = RR_OK;
+  double best = -1.0;
+  rr_tuning pick{};
+  // the tile and the persistent grid with the default superblock, then the
+  // superblock (and the tile-by-tile solve) for that tile and grid
+  const int tiles[2] = {64, 32};
+  const int grids[2] = {cus, 2 * cus};
+  for (int ti = 0; ti < 2 && st == RR_OK; ti++)
+    for (int gi = 0; gi < 2 && st == RR_OK; gi++) {
+      rr_tuning t{};
+      t.tile = tiles[ti];
+      t.grid = grids[gi];
+      double sc = 0;
+      st = trial(t, &sc);
+      if (st == RR_OK && sc >= 0 && (best < 0 || sc < best)) {
+        best = sc;
+        pick = t;
       }
-      rr_factors_free(h);
-      if (fs != RR_OK) { st = fs; break; }
-      // one pass of Algorithm 1 with a subspace iteration costs a factor and
-      // about five solves (sketch, two iteration solves, adjoint, recovery)
-      const double score = ms_f + 2.5 * (ms_s + ms_a);
-      if (best < 0 || score < best) {
-        best = score;
+    }
+  if (st == RR_OK && best >= 0) {
+    const int B = (2 * p->ny + pick.tile - 1) / pick.tile;
+    const int dflt = superblock_tiles(0, pick.tile, B);
+    const int sbs[4] = {-1, 2, 4, 8};
+    const rr_tuning base = pick;
+    for (int i = 0; i < 4 && st == RR_OK; i++) {
+      if (sbs[i] == dflt || (sbs[i] > 0 && sbs[i] > 2 * B)) continue;
+      rr_tuning t = base;
+      t.superblock = sbs[i];
+      double sc = 0;
+      st = trial(t, &sc);
+      if (st == RR_OK && sc >= 0 && sc < best) {
+        best = sc;
         pick = t;
       }
     }
@@ -843,6 +959,7 @@ rr_status rr_autotune(const rr_problem* p, const double* omega_re, const double*
   if (best < 0) return fail(RR_ERR_NOMEM, "autotune: no candidate fits in device memory");
   *out = pick;
   if (out_ms) *out_ms = best;
+  if (cache && *cache) cache_store(cache, key, pick, best);
   return RR_OK;
 }
 

@@ -30,7 +30,13 @@
 //            and the finalisation (flag 2; the diagonal tile 2, then 3 once
 //            its full inverses are stored)
 // so the chain from one diagonal block to the next carries one update GEMM,
-// one triangular solve and one T x T LU.  The tile of M itself is generated
+// one triangular solve and one T x T LU.  A diagonal tile's early updates are
+// split once more, so that no long task sits on that chain either:
+//   E'(m, m)  s <= m-3, issued two block steps ahead (flag 1)
+//   G(m, m)   s = m-2 on top of E'(m, m), issued one step ahead (flag 2)
+// and the diagonal worker adds s = m-1 before its LU.  With the superblock
+// solve (no chain tiles) the worker publishes only the block-inverse LU; the
+// full inverses of the diagonal tiles follow in a launch of their own.  The tile of M itself is generated
 // from the stencil in registers: the band is never read before it is final.
 // Every tile store is device-coherent (st_coherent) and goes through LDS so
 // that each store instruction writes whole lines: a tile is written twice
@@ -455,45 +461,55 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
 // cannot block it.
 //
 // Task decoding: slot -> (kind, r, t) for block step m.  Kinds: 0 = F,
-// 1 = E, 2 / 3 = the chain tiles of diagonal tile m (column / row side).
-//   slots 0 .. 2B-4: E of the tiles finalised at step m+1 (distance <= B-2),
-//     E(m+1, m+1) first (it feeds the next diagonal tile)
-//   slots 2B-3, 2B-2: F(m+1, m), F(m, m+1)
-//   slots 2B-1 .. 4B-4: F at distance 2 .. B
-//   slots 4B-3, 4B-2: the chain tiles of diagonal tile m
+// 1 = E (off-diagonal), 2 / 3 = the chain tiles of diagonal tile m (column /
+// row side), 4 = E' and 5 = G of a diagonal tile.
+//   slot 0: G(m+1, m+1) (it feeds the next diagonal tile)
+//   slot 1: E'(m+2, m+2)
+//   slots 2 .. 2B-3: E of the off-diagonal tiles finalised at step m+1
+//     (distance <= B-2)
+//   slots 2B-2, 2B-1: F(m+1, m), F(m, m+1)
+//   slots 2B .. 4B-3: F at distance 2 .. B
+//   slots 4B-2, 4B-1: the chain tiles of diagonal tile m
 // (B = 1: F(m+1, m), F(m, m+1) and the two chain tasks.)
 struct Task {
   int kind, r, t;
 };
+enum { TK_F = 0, TK_E = 1, TK_CHAIN_L = 2, TK_CHAIN_U = 3, TK_EDIAG = 4, TK_GDIAG = 5 };
 
-__host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B - 1 : 4; }
+__host__ __device__ inline int factor_slots(int B) { return B >= 2 ? 4 * B : 4; }
 
 __host__ __device__ inline Task decode(int slot, int m, int B) {
   if (B < 2) {
-    if (slot == 0) return {0, m + 1, m};
-    if (slot == 1) return {0, m, m + 1};
-    return {slot == 2 ? 2 : 3, m, m};
+    if (slot == 0) return {TK_F, m + 1, m};
+    if (slot == 1) return {TK_F, m, m + 1};
+    return {slot == 2 ? TK_CHAIN_L : TK_CHAIN_U, m, m};
   }
-  if (slot < 2 * B - 3) {
-    const int mm = m + 1;
-    if (slot == 0) return {1, mm, mm};
-    const int d = (slot + 1) >> 1;
-    return (slot & 1) ? Task{1, mm + d, mm} : Task{1, mm, mm + d};
+  if (slot == 0) return {TK_GDIAG, m + 1, m + 1};
+  if (slot == 1) return {TK_EDIAG, m + 2, m + 2};
+  if (slot < 2 * B - 2) {
+    const int mm = m + 1, d = slot >> 1;  // slots 2d, 2d+1 hold distance d
+    return (slot & 1) ? Task{TK_E, mm, mm + d} : Task{TK_E, mm + d, mm};
   }
-  if (slot == 2 * B - 3) return {0, m + 1, m};
-  if (slot == 2 * B - 2) return {0, m, m + 1};
-  if (slot < 4 * B - 3) {
-    const int f = slot - (2 * B - 1), d = 2 + (f >> 1);
-    return (f & 1) ? Task{0, m, m + d} : Task{0, m + d, m};
+  if (slot == 2 * B - 2) return {TK_F, m + 1, m};
+  if (slot == 2 * B - 1) return {TK_F, m, m + 1};
+  if (slot < 4 * B - 2) {
+    const int f = slot - 2 * B, d = 2 + (f >> 1);
+    return (f & 1) ? Task{TK_F, m, m + d} : Task{TK_F, m + d, m};
   }
-  return {slot == 4 * B - 3 ? 2 : 3, m, m};
+  return {slot == 4 * B - 2 ? TK_CHAIN_L : TK_CHAIN_U, m, m};
 }
 
-// E(r, t) has work when its early range s in [mx-B, m-2] is non-empty.
-__host__ __device__ inline bool has_early(int r, int t, int B) {
+// Update ranges s in [lo, hi] of the tasks of tile (r, t), m = min(r, t),
+// mx = max(r, t): all of them together cover [max(0, mx - B), m - 1].
+//   E (off-diagonal):  [max(0, mx - B), m - 2]
+//   E' (diagonal):     [max(0, m - B), m - 3]
+//   G (diagonal):      m - 2 alone, when in the band
+// F and the diagonal worker take s = m - 1.
+__host__ __device__ inline bool has_early(int r, int t, int B) {  // E or G
   int m = min(r, t), d = abs(r - t);
   return m >= 2 && d <= B - 2;
 }
+__host__ __device__ inline bool has_ediag(int m, int B) { return m >= 3 && B >= 3; }
 
 // Test hook (host only): the factor launch's ticket tasks of one shift, in
 // ticket order, as (kind, r, t) triples with the decoder above; tasks that
@@ -508,8 +524,10 @@ extern "C" int64_t rr_factor_schedule(int32_t B, int32_t NB, int32_t* out, int64
     for (int slot = 0; slot < slots; slot++) {
       const Task tk = decode(slot, m, B);
       if (tk.r < 0 || tk.r >= NB || tk.t >= NB) continue;
-      if (tk.kind == 1 && !has_early(tk.r, tk.t, B)) continue;
-      if (tk.kind >= 2 && tk.r == 0) continue;
+      if (tk.kind == TK_E && !has_early(tk.r, tk.t, B)) continue;
+      if (tk.kind == TK_GDIAG && !has_early(tk.r, tk.r, B)) continue;
+      if (tk.kind == TK_EDIAG && !has_ediag(tk.r, B)) continue;
+      if ((tk.kind == TK_CHAIN_L || tk.kind == TK_CHAIN_U) && tk.r == 0) continue;
       if (n < cap) {
         out[3 * n] = tk.kind;
         out[3 * n + 1] = tk.r;
@@ -585,8 +603,13 @@ __device__ __forceinline__ void update_gemms(Acc2<R>& acc, const FactorParams& P
   }
 }
 
+// Tile flags.  Off-diagonal: 1 = partial (E done), 3 = final.  Diagonal:
+// 1 = E' done, 2 = G done, 3 = block-inverse LU published, 4 = [U^-1 | L^-1]
+// published (only when chain tiles are formed).
+enum { FL_PARTIAL = 1, FL_PARTIAL2 = 2, FL_FINAL = 3, FL_DIAG_INV = 4 };
+
 // Wave 0 polls one optional flag (to extra_want) and the flags of tiles
-// (r, s) and (s, t), s in [s0, s1] (to 2 = final), one flag per lane so that
+// (r, s) and (s, t), s in [s0, s1] (to FL_FINAL), one flag per lane so that
 // the round trips of the atomic polls overlap (lane q takes flags q, q + 64,
 // ...), then lane 0 issues one acquire fence and the barrier hands the result
 // to every wave.
@@ -602,7 +625,7 @@ __device__ __forceinline__ void wait_inputs(const FactorParams& P, int w, int r,
     for (int q0 = 0; q0 < nq; q0 += 64) {
       const int q = q0 + lane;
       int* f = nullptr;
-      int want = 2;
+      int want = FL_FINAL;
       if (q == 0) {
         f = extra;
         want = extra_want;
@@ -707,20 +730,17 @@ __device__ __forceinline__ cplx<R>* lub_ptr(const FactorParams& P, int w, int s)
   return reinterpret_cast<cplx<R>*>(P.tiles) + idx * (T * T);
 }
 
-// Diagonal flags: 1 = partial (E done), 2 = block-inverse LU published,
-// 3 = [U^-1 | L^-1] published.  Off-diagonal tiles stop at 2 (final).
-enum { FL_PARTIAL = 1, FL_FINAL = 2, FL_DIAG_INV = 3 };
 
-// The tile (r, t) into the accumulators: the partial left by E(r, t), or
-// generated from the stencil.
+// The tile (r, t) into the accumulators: the partial whose flag reaches
+// `partial` (> 0), or the tile of M generated from the stencil (0).
 template <typename R, int T>
 __device__ __forceinline__ void load_tile(const FactorParams& P, Acc2<R>& acc, int w, int r,
-                                          int t, bool early, int rb, int cp) {
+                                          int t, int partial, int rb, int cp) {
   const int l = threadIdx.x & 63;
   const bool rowmajor = r < t;
-  if (!early && has_early(r, t, P.g.B)) {
+  if (partial > 0) {
     const cplx<R>* X = tile_ptr<R, T>(P, w, r, t);
-    wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), FL_PARTIAL);
+    wait_inputs(P, w, r, t, 0, -1, flag_ptr(P, w, r, t), partial);
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       const int c = 32 * cp + 16 * b + (l & 15);
@@ -769,7 +789,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     for (int m = 0; m < NB; m++) {
       cplx<R>* X = tile_ptr<R, T>(P, w, m, m);
       int* dflag = flag_ptr(P, w, m, m);
-      load_tile<R, T>(P, acc, w, m, m, false, rb, cp);
+      load_tile<R, T>(P, acc, w, m, m, has_early(m, m, B) ? FL_PARTIAL2 : 0, rb, cp);
       if (m >= 1) wait_inputs(P, w, m, m, m - 1, m - 1, nullptr, FL_FINAL);
       update_gemms<R, T, KU>(acc, P, w, m, m, max(0, m - 1), m - 1, rb, cp);
       acc_to_lds<R, T>(acc, lds, false, rb, cp);
@@ -779,6 +799,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       lu_blockinv<R, T, G::NW>(lds, G::LDT, P.status);
       lds_to_tile<R, T>(lds, lub_ptr<R, T>(P, w, m), false);
       publish(dflag, FL_FINAL);
+      if (P.g.P > 0) continue;  // the full inverse follows in k_diaginv
       inv_doubling<R, T, G::NW>(lds, G::LDT, aux);
       lds_to_tile<R, T>(lds, X, false);
       publish(dflag, FL_DIAG_INV);
@@ -797,7 +818,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     if (r < 0 || r >= NB || t >= NB) continue;
     const int m = min(r, t), mx = max(r, t);
     int* dflag = flag_ptr(P, w, m, m);
-    if (tk.kind >= 2) {
+    if (tk.kind == TK_CHAIN_L || tk.kind == TK_CHAIN_U) {
       // chain tiles of diagonal tile m: L_mm^-1 L_m,m-dd (kind 2) or
       // U_m-dd,m U_mm^-1 (kind 3), dd = 1 .. kChainD, with D_m in LDS; only
       // the tile-by-tile solve reads them
@@ -807,7 +828,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       __syncthreads();
       for (int dd = 1; dd <= BandGeom::kChainD && dd <= B && m - dd >= 0; dd++) {
         acc.zero();
-        if (tk.kind == 2) {
+        if (tk.kind == TK_CHAIN_L) {
           tile_gemm<R, T, KQ, false>(acc, lds, G::LDT, false, MK_UNIT_LOWER,
                                      tile_ptr<R, T>(P, w, m, m - dd), T, true, MK_NONE, rb, cp);
           stage_store<R, T>(acc, aux, chain_ptr<R, T>(P, w, m, chain_index(CH_FWD_L, dd)),
@@ -821,22 +842,39 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
       }
       continue;
     }
-    const bool early = tk.kind == 1;
-    if (early && !has_early(r, t, B)) continue;
+    const bool early = tk.kind != TK_F;  // E, E' or G: a partial tile
+    if (tk.kind == TK_E && !has_early(r, t, B)) continue;
+    if (tk.kind == TK_GDIAG && !has_early(r, t, B)) continue;
+    if (tk.kind == TK_EDIAG && !has_ediag(m, B)) continue;
     const bool rowmajor = r < t;  // U tiles
     cplx<R>* X = tile_ptr<R, T>(P, w, r, t);
-    // 1. the tile; 2. updates A_rt -= L_rs U_st: E takes s in [mx-B, m-2],
-    // F takes s = m-1 (whose inputs are final a block step before tile m is)
-    load_tile<R, T>(P, acc, w, r, t, early, rb, cp);
-    const int s_lo = early ? max(0, mx - B) : max(max(0, mx - B), m - 1);
-    const int s_hi = early ? m - 2 : m - 1;
+    // 1. the tile: E and E' start from the stencil, G from E' (if any), F
+    // from E (if any); 2. their updates A_rt -= L_rs U_st over the ranges
+    // above (F: s = m-1, whose inputs are final a block step before tile m)
+    int partial = 0, s_lo, s_hi, done = FL_PARTIAL;
+    if (tk.kind == TK_E) {
+      s_lo = max(0, mx - B);
+      s_hi = m - 2;
+    } else if (tk.kind == TK_EDIAG) {
+      s_lo = max(0, m - B);
+      s_hi = m - 3;
+    } else if (tk.kind == TK_GDIAG) {
+      partial = has_ediag(m, B) ? FL_PARTIAL : 0;
+      s_lo = s_hi = m - 2;
+      done = FL_PARTIAL2;
+    } else {
+      partial = has_early(r, t, B) ? FL_PARTIAL : 0;
+      s_lo = max(max(0, mx - B), m - 1);
+      s_hi = m - 1;
+    }
+    load_tile<R, T>(P, acc, w, r, t, partial, rb, cp);
     if (s_lo <= s_hi) wait_inputs(P, w, r, t, s_lo, s_hi, nullptr, FL_FINAL);
     update_gemms<R, T, KU>(acc, P, w, r, t, s_lo, s_hi, rb, cp);
     acc_to_lds<R, T>(acc, lds, false, rb, cp);  // column-major in every case
     if (early) {
       __syncthreads();
       lds_to_tile<R, T>(lds, X, rowmajor);
-      publish(flag_ptr(P, w, r, t), FL_PARTIAL);
+      publish(flag_ptr(P, w, r, t), done);
       continue;
     }
     // 3. finalise: a triangular solve with the block-inverse LU of tile m
@@ -867,6 +905,23 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
                         cp);
     }
   }
+}
+
+// Full inverses [U^-1 | L^-1] of the diagonal tiles from their published
+// block-inverse LUs (inv_doubling), one workgroup per (shift, block row),
+// after the factorisation: the superblock solve's diagonal blocks.
+template <typename R, int T>
+__global__ __launch_bounds__(FGeom<T>::NT) void k_diaginv(FactorParams P) {
+  typedef FGeom<T> G;
+  extern __shared__ __align__(16) char smem_raw[];
+  cplx<R>* lds = reinterpret_cast<cplx<R>*>(smem_raw);  // T x LDT
+  cplx<R>* aux = lds + T * G::LDT;
+  const int64_t id = blockIdx.x;
+  const int m = (int)(id % P.g.NB), w = (int)(id / P.g.NB);
+  tile_to_lds<R, T>(lub_ptr<R, T>(P, w, m), lds);
+  __syncthreads();
+  inv_doubling<R, T, G::NW>(lds, G::LDT, aux);
+  lds_to_tile<R, T>(lds, tile_ptr<R, T>(P, w, m, m), false);
 }
 
 // Tile `slot` of block row r's superblock-inverse area (BandGeom::sb_slot).
@@ -963,6 +1018,9 @@ static hipError_t launch_factor_t(const FactorParams& P, int grid, hipStream_t s
   if (ev && ev[0]) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_factor<R, T>), dim3(grid), dim3(FGeom<T>::NT), lds, s, P);
   if (ev && ev[1]) (void)hipEventRecord(ev[1], s);
+  if (P.g.P > 0)  // the diagonal tiles' full inverses
+    hipLaunchKernelGGL((k_diaginv<R, T>), dim3((unsigned)((int64_t)P.n_omega * P.g.NB)),
+                       dim3(FGeom<T>::NT), lds, s, P);
   if (P.g.P > 1) {  // the superblocks' diagonal inverses, for the superblock solve
     const int64_t nblk = (int64_t)P.n_omega * P.g.NS() * 2 * (P.g.P - 1);
     hipLaunchKernelGGL((k_sbinv<R, T>), dim3((unsigned)nblk), dim3(FGeom<T>::NT), lds, s, P);
@@ -981,17 +1039,21 @@ hipError_t prepare_factor(int T, bool fp32) {
     if (T == 64) {
       e = set((const void*)k_factor<float, 64>, factor_lds<float, 64>());
       if (e == hipSuccess) e = set((const void*)k_sbinv<float, 64>, factor_lds<float, 64>());
+      if (e == hipSuccess) e = set((const void*)k_diaginv<float, 64>, factor_lds<float, 64>());
     } else if (T == 32) {
       e = set((const void*)k_factor<float, 32>, factor_lds<float, 32>());
       if (e == hipSuccess) e = set((const void*)k_sbinv<float, 32>, factor_lds<float, 32>());
+      if (e == hipSuccess) e = set((const void*)k_diaginv<float, 32>, factor_lds<float, 32>());
     }
   } else {
     if (T == 64) {
       e = set((const void*)k_factor<double, 64>, factor_lds<double, 64>());
       if (e == hipSuccess) e = set((const void*)k_sbinv<double, 64>, factor_lds<double, 64>());
+      if (e == hipSuccess) e = set((const void*)k_diaginv<double, 64>, factor_lds<double, 64>());
     } else if (T == 32) {
       e = set((const void*)k_factor<double, 32>, factor_lds<double, 32>());
       if (e == hipSuccess) e = set((const void*)k_sbinv<double, 32>, factor_lds<double, 32>());
+      if (e == hipSuccess) e = set((const void*)k_diaginv<double, 32>, factor_lds<double, 32>());
     }
   }
   return e;

@@ -91,13 +91,47 @@ __device__ __forceinline__ void sc_load_b(SChunk<R, T, NCB>& c, const cplx<R>* V
     for (int q = 0; q < QC; q++) c.b[cb][q] = V[(4 * (q0 + q) + (l >> 4)) * NP + 16 * cb + (l & 15)];
 }
 
-template <typename R, int T, int NCB, bool CA, bool SUB>
-__device__ __forceinline__ void sc_mma(typename Mf<R>::v4 (&re)[NCB], typename Mf<R>::v4 (&im)[NCB],
-                                       const SChunk<R, T, NCB>& c) {
+// Complex products with three real MFMAs instead of four (Gauss): with
+// a = ar + i ai (ai negated when CA conjugates a) and b = br + i bi,
+//   p1 += ar br,  p2 += ai bi,  p3 += (ar + ai)(br + bi)
+// and at the end re = p1 - p2, im = p3 - p1 - p2 (sc_finish).  The sums cost
+// one add per operand element; the error of the imaginary part is bounded by
+// a small multiple of eps (|ar| + |ai|)(|br| + |bi|), like the four-product
+// form's up to a constant.  Flops are still counted as 8 per complex FMA.
+template <typename R, int NCB>
+struct SAcc {
+  typename Mf<R>::v4 p1[NCB], p2[NCB], p3[NCB];
+  __device__ __forceinline__ void zero() {
 #pragma unroll
-  for (int q = 0; q < ss_qc<R, T, NCB>(); q++)
+    for (int c = 0; c < NCB; c++)
 #pragma unroll
-    for (int cb = 0; cb < NCB; cb++) cmfma<R, CA, SUB>(re[cb], im[cb], c.a[q], c.b[cb][q]);
+      for (int e = 0; e < 4; e++) { p1[c][e] = 0; p2[c][e] = 0; p3[c][e] = 0; }
+  }
+};
+
+template <typename R, int T, int NCB, bool CA>
+__device__ __forceinline__ void sc_mma(SAcc<R, NCB>& acc, const SChunk<R, T, NCB>& c) {
+#pragma unroll
+  for (int q = 0; q < ss_qc<R, T, NCB>(); q++) {
+    const R ar = c.a[q].re, ai = CA ? -c.a[q].im : c.a[q].im;
+    const R sa = ar + ai;
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb++) {
+      const R br = c.b[cb][q].re, bi = c.b[cb][q].im;
+      acc.p1[cb] = Mf<R>::op(ar, br, acc.p1[cb]);
+      acc.p2[cb] = Mf<R>::op(ai, bi, acc.p2[cb]);
+      acc.p3[cb] = Mf<R>::op(sa, br + bi, acc.p3[cb]);
+    }
+  }
+}
+
+// Element e of column block cb: (re, im) of the accumulated product,
+// negated when SUB.
+template <typename R, int NCB>
+__device__ __forceinline__ cplx<R> sc_finish(const SAcc<R, NCB>& acc, int cb, int e, bool sub) {
+  const R re = acc.p1[cb][e] - acc.p2[cb][e];
+  const R im = acc.p3[cb][e] - acc.p1[cb][e] - acc.p2[cb][e];
+  return sub ? cplx<R>{-re, -im} : cplx<R>{re, im};
 }
 
 }  // namespace
@@ -170,7 +204,6 @@ constexpr size_t ssolve_lds() {  // per-wave partial sums, the summed piece, its
 template <typename R, int T, int NP, bool ADJ>
 __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
   if (P.skip && __hip_atomic_load(P.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  typedef typename Mf<R>::v4 v4;
   constexpr int NCB = NP / 16;
   constexpr int NT = 64 * kSsWaves;
   constexpr int RPT = T / 16;  // 16-row blocks per tile
@@ -279,11 +312,8 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
       else ss_wait(counter(1, S + 1, 1), npc, P.status);
     }
     if (s < NB) {
-      v4 are[NCB], aim[NCB];
-#pragma unroll
-      for (int c = 0; c < NCB; c++)
-#pragma unroll
-        for (int e = 0; e < 4; e++) { are[c][e] = 0; aim[c][e] = 0; }
+      SAcc<R, NCB> acc;
+      acc.zero();
       if (phase == 0 && second) {  // the first sweep's y_s
         const cplx<R>* ys = xw + (int64_t)s * T * NP;
         for (int idx = threadIdx.x; idx < 16 * NP; idx += NT) {
@@ -292,25 +322,22 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
           bin[idx] = make_double2((double)v.re, (double)v.im);
         }
       }
-      //   phase A:  acc = -sum_t T_st x_t       (the waves take the tiles in turn)
-      //   phase B:  acc = sum_j (D-hat^-1)_ij c_j
+      //   phase A:  -sum_t T_st x_t       (the waves take the tiles in turn)
+      //   phase B:  sum_j (D-hat^-1)_ij c_j
       if (nch > 0) load(c0, 0, false, true);
       if constexpr (NCH == 1) {  // one buffer: a chunk is a whole tile
         for (int idx = 0; idx < nch; idx++) {
           if (idx > 0) load(c0, idx, true, true);
-          if (phase == 0) sc_mma<R, T, NCB, ADJ, true>(are, aim, c0);
-          else sc_mma<R, T, NCB, ADJ, false>(are, aim, c0);
+          sc_mma<R, T, NCB, ADJ>(acc, c0);
         }
       } else {                         // two buffers, one chunk ahead
         SChunk<R, T, NCB> c1;
         for (int idx = 0; idx < nch; idx += 2) {
           if (idx + 1 < nch) load(c1, idx + 1, true, true);
-          if (phase == 0) sc_mma<R, T, NCB, ADJ, true>(are, aim, c0);
-          else sc_mma<R, T, NCB, ADJ, false>(are, aim, c0);
+          sc_mma<R, T, NCB, ADJ>(acc, c0);
           if (idx + 1 < nch) {
             if (idx + 2 < nch) load(c0, idx + 2, true, true);
-            if (phase == 0) sc_mma<R, T, NCB, ADJ, true>(are, aim, c1);
-            else sc_mma<R, T, NCB, ADJ, false>(are, aim, c1);
+            sc_mma<R, T, NCB, ADJ>(acc, c1);
           }
         }
       }
@@ -320,7 +347,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
 #pragma unroll
         for (int e = 0; e < 4; e++)
           red[(wave * 16 + Mf<R>::row(l, e)) * NP + 16 * c + (l & 15)] =
-              cplx<R>{are[c][e], aim[c][e]};
+              sc_finish<R, NCB>(acc, c, e, phase == 0);
       __syncthreads();
       for (int idx = threadIdx.x; idx < 16 * NP; idx += NT) {
         R sr = 0, sm = 0;

@@ -8,15 +8,19 @@ s in [max(0, max(r, t) - B), min(r, t) - 1], then finalises it against the
 LU of diagonal tile m = min(r, t).  The launch splits each off-diagonal tile
 into an early task E (all updates but the last, written as a partial tile)
 and a final task F (the last update, the triangular solve, and for distances
-up to three a chain tile with the full inverse of tile m); diagonal tile m is
-factored by a worker of its own, and two more ticket tasks form its chain
-tiles.  The waits each task makes are restated here from the kernel:
+up to three a chain tile with the full inverse of tile m); a diagonal tile's
+early updates are split into E' (s <= m - 3) and G (s = m - 2, on top of
+E'), and the tile is factored by a worker of its own (s = m - 1, then the
+LU); two more ticket tasks form its chain tiles.  The waits each task makes
+are restated here from the kernel:
 
   E(r, t)        waits on the final L_rs, U_st of its early updates;
+  E'(m, m)       waits on the final L_ms, U_sm, s <= m - 3;
+  G(m, m)        waits on E'(m, m) and the final L_m,m-2, U_m-2,m;
   F(r, t)        waits on E(r, t), the final L_rs, U_st of s = m - 1, the
                  block-inverse LU of diagonal tile m, and (distance <= 3) the
                  full inverse of tile m;
-  diagonal m     (worker, in order m = 0, 1, ...) waits on E(m, m) and the
+  diagonal m     (worker, in order m = 0, 1, ...) waits on G(m, m) and the
                  final L_m,m-1, U_m-1,m;
   chain task m   waits on the full inverse of tile m and reads the final
                  tiles (m, m - d), (m - d, m) for d <= 3 without a wait of
@@ -35,6 +39,7 @@ import pytest
 from paper_1902_01458_amd import _lib
 
 CHAIN_D = 3  # chain tiles are formed for distances 1 .. 3
+F, E, CHAIN_L, CHAIN_U, EDIAG, GDIAG = 0, 1, 2, 3, 4, 5  # task kinds
 
 
 def schedule(B, NB):
@@ -64,6 +69,15 @@ def has_early(r, t, B):
     return lo <= hi
 
 
+def ediag_range(m, B):
+    return max(0, m - B), m - 3
+
+
+def has_ediag(m, B):
+    lo, hi = ediag_range(m, B)
+    return lo <= hi
+
+
 CASES = [(B, NB) for B in (1, 2, 3, 4, 5, 8, 11) for NB in sorted({1, 2, 3, B, B + 1, 2 * B + 3, 24})]
 
 
@@ -77,10 +91,11 @@ def test_rejects_bad_sizes():
 def test_every_task_once(B, NB):
     tasks = schedule(B, NB)
     assert len(set(tasks)) == len(tasks)
-    want = {(0, r, t) for r, t in band_tiles(B, NB)}
-    want |= {(1, r, t) for r in range(NB) for t in range(NB)
-             if abs(r - t) <= B and has_early(r, t, B)}
-    want |= {(k, m, m) for m in range(1, NB) for k in (2, 3)}
+    want = {(F, r, t) for r, t in band_tiles(B, NB)}
+    want |= {(E, r, t) for r, t in band_tiles(B, NB) if has_early(r, t, B)}
+    want |= {(EDIAG, m, m) for m in range(NB) if has_ediag(m, B)}
+    want |= {(GDIAG, m, m) for m in range(NB) if has_early(m, m, B)}
+    want |= {(k, m, m) for m in range(1, NB) for k in (CHAIN_L, CHAIN_U)}
     assert set(tasks) == want
 
 
@@ -97,7 +112,8 @@ def test_one_worker_finishes_and_reads_are_ordered(B, NB):
         return 1 << keys[key]
 
     final = {}      # (r, t) -> knowledge at its final publish (diagonal: LU published)
-    partial = {}    # (r, t) -> knowledge at E's publish
+    partial = {}    # (r, t) -> knowledge at E's publish (diagonal: E-prime's)
+    partial2 = {}   # (m, m) -> knowledge at G's publish
     dinv = {}       # m -> knowledge at the full-inverse publish
 
     def need_final(r, t):
@@ -107,9 +123,9 @@ def test_one_worker_finishes_and_reads_are_ordered(B, NB):
         """The diagonal worker's step m, if its inputs are published."""
         k = dinv[m - 1] if m >= 1 else 0
         if has_early(m, m, B):
-            if (m, m) not in partial:
+            if (m, m) not in partial2:
                 return False
-            k |= partial[(m, m)]
+            k |= partial2[(m, m)]
         if m >= 1:
             for key in ((m, m - 1), (m - 1, m)):
                 if key not in final:
@@ -131,10 +147,14 @@ def test_one_worker_finishes_and_reads_are_ordered(B, NB):
         m = min(r, t)
         k = 0
         waits = []
-        if kind == 1:
-            lo, hi = early_range(r, t, B)
+        if kind in (E, EDIAG):
+            lo, hi = early_range(r, t, B) if kind == E else ediag_range(m, B)
             waits = [("F", r, s) for s in range(lo, hi + 1)] + [("F", s, t) for s in range(lo, hi + 1)]
-        elif kind == 0:
+        elif kind == GDIAG:
+            if has_ediag(m, B):
+                waits.append(("E", m, m))
+            waits += [("F", m, m - 2), ("F", m - 2, m)]
+        elif kind == F:
             lo, hi = update_range(r, t, B)
             if has_early(r, t, B):
                 waits.append(("E", r, t))
@@ -148,20 +168,24 @@ def test_one_worker_finishes_and_reads_are_ordered(B, NB):
         for w, a, b in waits:
             if w == "E":
                 got = partial.get((a, b))
+            elif w == "G":
+                got = partial2.get((a, b))
             elif w == "D":
                 got = dinv.get(a)
             else:
                 got = need_final(a, b)
             assert got is not None, f"ticket {i} {(kind, r, t)} waits on unpublished {(w, a, b)}"
             k |= got | bit((w, a, b))
-        if kind == 1:
+        if kind in (E, EDIAG):
             partial[(r, t)] = k | bit(("E", r, t))
-        elif kind == 0:
+        elif kind == GDIAG:
+            partial2[(r, t)] = k | bit(("G", r, t))
+        elif kind == F:
             final[(r, t)] = k | bit(("F", r, t))
         else:
             # the chain task's reads without waits of their own
             for d in range(1, min(CHAIN_D, B, m) + 1):
-                tile = (m, m - d) if kind == 2 else (m - d, m)
+                tile = (m, m - d) if kind == CHAIN_L else (m - d, m)
                 assert k & bit(("F",) + tile), f"chain task {(kind, m)} reads {tile} unordered"
     advance_diagonal()
     assert next_diag == NB

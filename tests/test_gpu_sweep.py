@@ -69,6 +69,32 @@ def test_autotuner_pick_runs_and_matches_oracle():
         assert gain_errors(to_np(out["sigma_AV"][i]), r.sigma_AV).max() <= 1e-10
 
 
+def test_autotuner_cache_skips_the_trials(tmp_path, monkeypatch):
+    """With RR_AUTOTUNE_CACHE set, the first call runs the trials (tile, grid,
+    then superblock) and stores its pick in the JSON file; a second call with
+    the same key returns the same pick from the file without running any
+    trial (orders of magnitude faster), and a different k is a new key."""
+    import time
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("RR_AUTOTUNE_CACHE", str(cache))
+    w = W.small("atc", 40, 32, nu=1e-2, omegas=(0.6, 2.2), k=8, q=0)
+    prob = rr().BurgersProblem.from_workload(w)
+    t0 = time.perf_counter()
+    first = rr().autotune(prob, list(w.omegas), w.k, "fp64")
+    t1 = time.perf_counter()
+    second = rr().autotune(prob, list(w.omegas), w.k, "fp64")
+    t2 = time.perf_counter()
+    assert first == second
+    assert first["superblock"] in (-1, 0, 2, 4, 8) and first["tile"] in (32, 64)
+    assert (t2 - t1) * 20 < (t1 - t0), (t1 - t0, t2 - t1)
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1
+    (key, val), = entries.items()
+    assert key.endswith("|40x32|w2|k8|fp64") and val["tile"] == first["tile"]
+    rr().autotune(prob, list(w.omegas), 6, "fp64")  # another key: trials, a second entry
+    assert len(json.loads(cache.read_text())) == 2
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-8)])
 def test_cfg2_sweep_matches_oracle(prec, tol):
     """Config 2: 256 x 128 grid (n = 65536), 64 log-spaced shifts in [0.1, 10],
