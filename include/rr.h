@@ -153,9 +153,33 @@ typedef struct {
                             default (256 rows per step, at most the half-band's
                             tiles); negative = one block row per step (the
                             tile-by-tile recurrence with chain tiles)          */
+  int32_t solver;        /* RR_SOLVER_BAND_LU (default): the band LU of
+                            M(omega) serves every solve (Section 3.1).
+                            RR_SOLVER_BICGSTAB / RR_SOLVER_GMRES: no LU at
+                            all; every solve of Algorithm 1 is a Krylov
+                            iteration with M applied from the stencil and the
+                            preconditioner `precond` (the option the paper
+                            names at the end of Section 3.2, for operators
+                            whose band LU does not fit in memory).  FP64 only
+                            (prec must be RR_FP64); tile, grid, superblock
+                            and the refinement fields are then unused, and
+                            GMRES restarts every gmres_restart steps          */
+  int32_t precond;       /* Krylov only: RR_PRECOND_JACOBI (default; the 2 x 2
+                            node blocks of M inverted) or RR_PRECOND_ILU0
+                            (block ILU(0) in the natural node order)          */
+  int32_t krylov_maxit;  /* Krylov only: most iterations per solve (GMRES:
+                            inner steps, rounded up to whole restarts);
+                            default 1000, at most 100000.  The launches are
+                            fixed (graph-safe) and skip their work once every
+                            system has converged; a system still above
+                            tolerance at the end latches RR_ERR_NOT_CONVERGED */
+  double  krylov_tol;    /* Krylov only: a system has converged when
+                            ||b - M x|| <= tol ||b|| (default 1e-10)          */
 } rr_tuning;
 
 enum { RR_REFINE_PLAIN = 0, RR_REFINE_GMRES = 1 };
+enum { RR_SOLVER_BAND_LU = 0, RR_SOLVER_BICGSTAB = 1, RR_SOLVER_GMRES = 2 };
+enum { RR_PRECOND_JACOBI = 0, RR_PRECOND_ILU0 = 1 };
 
 /* Test matrices Omega of Algorithm 1 step 1 (Section 2.2.2), each weighted by
  * the problem's Phi (eq. 10) when it has one.  RR_TM_RADEMACHER: real +-1
@@ -402,6 +426,14 @@ rr_status rr_philox_raw(uint32_t* out_dev, int64_t count, uint32_t c1, uint32_t 
                         uint32_t k1, void* stream);
 rr_status rr_sketch(const rr_problem* p, int32_t k, uint64_t seed, rr_test_matrix kind,
                     int32_t zeta, double* theta, void* stream);
+
+/* Test hook: Y = K^-1 X (adjoint: K^-H X) with the preconditioner K of a
+ * Krylov handle (rr_tuning.solver), for k columns of every shift; X and Y
+ * are device blocks of n_omega * k * n complex (k-column blocks per shift,
+ * the layout of every block), and Y may be X.  RR_ERR_INVALID for a band-LU
+ * handle or k outside [1, k_max]. */
+rr_status rr_precond_apply(rr_factors* f, int32_t k, int32_t adjoint, const double* X, double* Y,
+                           void* stream);
 
 /* Test hook for the factorisation's task order (host only, no device call).
  * Writes the ticket tasks of one shift of a band of B tiles each side and NB

@@ -15,6 +15,8 @@ RR_FP64, RR_MIXED = 0, 1
 RR_RESP_AV, RR_RESP_QU, RR_RESP_NONE = 0, 1, 2
 TEST_MATRICES = {"gaussian": 0, "rademacher": 1, "sparse": 2, "orthonormal": 3}
 REFINE_METHODS = {"plain": 0, "gmres": 1}
+SOLVERS = {"lu": 0, "bicgstab": 1, "gmres": 2}
+PRECONDS = {"jacobi": 0, "ilu0": 1}
 
 # every symbol include/rr.h declares (the last three are test hooks)
 EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sketch_solve",
@@ -22,7 +24,7 @@ EXPORTS = ("rr_burgers_coeffs", "rr_apply", "rr_factor", "rr_refactor", "rr_sket
            "rr_bytes", "rr_factors_free", "rr_set_allocator", "rr_factor_bytes", "rr_graph_capture",
            "rr_graph_launch", "rr_graph_free", "rr_autotune", "rr_last_error", "rr_philox_raw",
            "rr_sketch", "rr_factor_schedule", "rr_set_test_matrix", "rr_set_jacobi_sweeps",
-           "rr_grad_noalloc", "rr_set_timing_events")
+           "rr_grad_noalloc", "rr_set_timing_events", "rr_precond_apply")
 
 
 class RRError(RuntimeError):
@@ -46,7 +48,9 @@ class Tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("refine_iters", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("refine_tol_sketch", ctypes.c_double), ("refine_method", ctypes.c_int32),
-                ("gmres_restart", ctypes.c_int32), ("superblock", ctypes.c_int32)]
+                ("gmres_restart", ctypes.c_int32), ("superblock", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("krylov_maxit", ctypes.c_int32), ("krylov_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -88,6 +92,7 @@ def lib() -> ctypes.CDLL:
         "rr_set_test_matrix": [vp, ctypes.c_int, i32],
         "rr_set_jacobi_sweeps": [vp, i32],
         "rr_set_timing_events": [vp, vp, vp, vp, vp],
+        "rr_precond_apply": [vp, i32, i32, vp, vp, vp],
         "rr_factor_bytes": [i32, i32, i32, i32, ctypes.c_int, i32],
         "rr_factor_schedule": [i32, i32, vp, i64],
         "rr_set_allocator": [ALLOC_FN, FREE_FN, vp],

@@ -127,7 +127,8 @@ class Factors:
                  tile: int = 0, grid: int = 0, refine_iters: int = 0, refine_tol: float = 0.0,
                  refine_tol_sketch: float = 0.0, stream=None, discount: float = 0.0,
                  test_matrix: str = "gaussian", zeta: int = 0, refine_method: str = "plain",
-                 gmres_restart: int = 0, superblock: int = 0):
+                 gmres_restart: int = 0, superblock: int = 0, solver: str = "lu",
+                 precond: str = "jacobi", krylov_maxit: int = 0, krylov_tol: float = 0.0):
         # discount beta: the paper's discounted resolvent (Section 2.1),
         # M = i omega I - (L - beta I), i.e. the shift omega - i beta here
         om = np.asarray(omegas, dtype=np.complex128).reshape(-1) - 1j * discount
@@ -143,8 +144,12 @@ class Factors:
         # refine_method "gmres": GMRES-IR corrections (mixed precision), for
         # shifts where plain refinement with the FP32 LU stalls
         # superblock: block rows per solve step (0: default, < 0: one at a time)
+        # solver "bicgstab" / "gmres": no band LU; every solve is a Krylov
+        # iteration preconditioned by `precond` ("jacobi" or "ilu0"), FP64
         tune = _lib.Tuning(tile, grid, refine_iters, refine_tol, refine_tol_sketch,
-                           _lib.REFINE_METHODS[refine_method], gmres_restart, superblock)
+                           _lib.REFINE_METHODS[refine_method], gmres_restart, superblock,
+                           _lib.SOLVERS[solver], _lib.PRECONDS[precond], krylov_maxit,
+                           krylov_tol)
         ps = prob.c_struct()
         check(lib().rr_factor(ctypes.byref(ps), re.ctypes.data_as(ctypes.c_void_p),
                               im.ctypes.data_as(ctypes.c_void_p), self.n_omega, k_max,
@@ -173,6 +178,16 @@ class Factors:
         """Sweep cap of the k x k Jacobi SVD (default 40); a sweep that still
         rotates at the cap is reported as RR_ERR_NOT_CONVERGED by check()."""
         check(lib().rr_set_jacobi_sweeps(self.handle, sweeps))
+
+    def precond_apply(self, X: torch.Tensor, adjoint: bool = False, out=None) -> torch.Tensor:
+        """Y = K^-1 X (or K^-H X) with the Krylov handle's preconditioner, for a
+        (n_omega, k, n) complex128 block (rr_precond_apply; a test hook)."""
+        X = X.contiguous()
+        Y = torch.empty_like(X) if out is None else out
+        check(lib().rr_precond_apply(self.handle, X.shape[1], 1 if adjoint else 0,
+                                     ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                     ctypes.c_void_p(_stream(None))))
+        return Y
 
     # -- lifetime ----------------------------------------------------------
     def free(self):

@@ -78,7 +78,9 @@ void free_all(rr_factors* f) {
                 f->theta,
                 f->work1, f->work2, f->work3, f->small.partial, f->small.G, f->small.R,
                 f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->small.shifted, f->grad_partial,
-                f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial};
+                f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial,
+                f->pc_dinv, f->kv[0], f->kv[1], f->kv[2], f->kv[3], f->kv[4], f->kv[5],
+                f->kv[6], f->kpart, f->kscal, f->kbnorm, f->kactive};
   for (void* p : ps) {
     if (!p) continue;
     if (f->dealloc) f->dealloc(p, f->alloc_ctx);
@@ -121,7 +123,11 @@ hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStr
   const uint32_t* skip = conv_word(f);
   auto V = [&](int i) { return g.V + 2 * i * vstride; };
   hipError_t e = launch_fill_u32((uint32_t*)g.H, 0u, (int64_t)n_omega * k * (m + 1) * m * 4, s);
+  // the preconditioner: the FP32 band LU (GMRES-IR), or the Krylov handle's K
   auto solve32 = [&](const double* in, double* out) {
+    if (f->solver != RR_SOLVER_BAND_LU)
+      return launch_pc_apply(opdesc(f), f->precond, n_omega, k, adjoint, f->pc_dinv, in, out,
+                             nullptr, skip, s);
     return launch_solve(f->geom, f->n, n_omega, k, true, f->tiles, adjoint, in, blk, out, f->xs,
                         f->cbuf, f->flags, ticket_word(f), st_word(f), f->solve_grid, s, skip);
   };
@@ -143,12 +149,90 @@ hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStr
   return e;
 }
 
+// X = M^-1 Bm (or M^-H Bm) without the LU: preconditioned BiCGStab or
+// restarted GMRES (left-preconditioned, the GMRES-IR cycle with K in place
+// of the FP32 LU), one system per (shift, column), from x = 0 until
+// ||b - M x|| <= krylov_tol ||b||.  A fixed number of launches; all of them
+// skip their work once every system has converged.
+rr_status krylov_solve(rr_factors* f, int k, int adjoint, const double* Bm, int64_t bstride,
+                       double* X, hipStream_t s) {
+  const OpDesc op = opdesc(f);
+  const int nw = f->n_omega, N = nw * k;
+  const int64_t n = f->n, total = (int64_t)nw * k * n;
+  const double tol = f->krylov_tol;
+  uint32_t* conv = conv_word(f);
+  uint32_t* act = f->kactive;
+  uint32_t* st = st_word(f);
+  double* r = f->kv[0];
+  RR_HIP(launch_fill_u32(conv, 0u, 1, s));
+  RR_HIP(launch_fill_u32((uint32_t*)X, 0u, total * 4, s));  // x = 0
+  // r = b - M 0 = b (the apply also spreads a right-hand side shared by the shifts)
+  RR_HIP(launch_apply(op, f->omega, nw, k, adjoint, X, Bm, bstride, r, s));
+  RR_HIP(launch_kdot(n, nw, k, 1, r, r, nullptr, nullptr, f->kpart, nullptr, nullptr, s));
+  RR_HIP(launch_bicg_scalars(N, n, 0, 0, tol, f->kpart, f->kscal, f->kbnorm, act, conv, st,
+                             nullptr, s));
+  if (f->solver == RR_SOLVER_BICGSTAB) {
+    double *rh = f->kv[1], *p = f->kv[2], *v = f->kv[3], *y = f->kv[4], *z = f->kv[5],
+           *t = f->kv[6];
+    RR_HIP(launch_kcopy(total, r, rh, s));
+    RR_HIP(launch_fill_u32((uint32_t*)p, 0u, total * 4, s));
+    RR_HIP(launch_fill_u32((uint32_t*)v, 0u, total * 4, s));
+    for (int it = 0; it < f->krylov_maxit; it++) {
+      // rho = <rhat, r>, beta; p = r + beta (p - omega v); y = K^-1 p; v = M y
+      RR_HIP(launch_kdot(n, nw, k, 1, rh, r, nullptr, nullptr, f->kpart, act, conv, s));
+      RR_HIP(launch_bicg_scalars(N, n, 1, it, tol, f->kpart, f->kscal, f->kbnorm, act, conv, st,
+                                 conv, s));
+      RR_HIP(launch_bicg_vec(0, n, nw, k, f->kscal, r, v, nullptr, nullptr, p, act, conv, s));
+      RR_HIP(launch_pc_apply(op, f->precond, nw, k, adjoint, f->pc_dinv, p, y, act, conv, s));
+      RR_HIP(launch_apply(op, f->omega, nw, k, adjoint, y, nullptr, 0, v, s, conv));
+      // alpha = rho / <rhat, v>; s = r - alpha v (kept in r)
+      RR_HIP(launch_kdot(n, nw, k, 1, rh, v, nullptr, nullptr, f->kpart, act, conv, s));
+      RR_HIP(launch_bicg_scalars(N, n, 2, it, tol, f->kpart, f->kscal, f->kbnorm, act, conv, st,
+                                 conv, s));
+      RR_HIP(launch_bicg_vec(1, n, nw, k, f->kscal, nullptr, v, nullptr, nullptr, r, act, conv, s));
+      // z = K^-1 s; t = M z; omega = <t, s> / <t, t>
+      RR_HIP(launch_pc_apply(op, f->precond, nw, k, adjoint, f->pc_dinv, r, z, act, conv, s));
+      RR_HIP(launch_apply(op, f->omega, nw, k, adjoint, z, nullptr, 0, t, s, conv));
+      RR_HIP(launch_kdot(n, nw, k, 2, t, r, t, t, f->kpart, act, conv, s));
+      RR_HIP(launch_bicg_scalars(N, n, 3, it, tol, f->kpart, f->kscal, f->kbnorm, act, conv, st,
+                                 conv, s));
+      // x += alpha y + omega z; r = s - omega t; then the convergence test
+      RR_HIP(launch_bicg_vec(2, n, nw, k, f->kscal, y, z, t, X, r, act, conv, s));
+      RR_HIP(launch_kdot(n, nw, k, 1, r, r, nullptr, nullptr, f->kpart, act, conv, s));
+      RR_HIP(launch_bicg_scalars(N, n, 4, it, tol, f->kpart, f->kscal, f->kbnorm, act, conv, st,
+                                 conv, s));
+    }
+  } else {
+    const int m = f->gm.m;
+    const int cycles = (f->krylov_maxit + m - 1) / m;
+    for (int c = 0; c <= cycles; c++) {
+      if (c > 0) {  // r = b - M x and the convergence test
+        RR_HIP(launch_apply(op, f->omega, nw, k, adjoint, X, Bm, bstride, r, s, conv));
+        RR_HIP(launch_kdot(n, nw, k, 1, r, r, nullptr, nullptr, f->kpart, act, conv, s));
+        RR_HIP(launch_bicg_scalars(N, n, 4, c, tol, f->kpart, f->kscal, f->kbnorm, act, conv, st,
+                                   conv, s));
+      }
+      if (c == cycles) break;
+      RR_HIP(gmres_correction(f, k, adjoint, r, s));  // r <- m steps of GMRES on K^-1 M d = K^-1 r
+      RR_HIP(launch_bicg_vec(3, n, nw, k, nullptr, r, nullptr, nullptr, X, nullptr, act, conv, s));
+    }
+  }
+  RR_HIP(launch_latch_live(N, act, st, ST_NOT_CONVERGED, s));
+  return RR_OK;
+}
+
 // X = M^-1 Bm (or M^-H): one FP64 band solve, or FP32 solves with FP64
 // residual refinement to `tol`.  Bm's blocks are bstride apart (0 = shared by
 // all shifts).  The mixed loop has a fixed number of launches; once every
 // column of every shift has converged the remaining ones return at once.
 rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t bstride,
                     double* X, double tol, hipStream_t s) {
+  if (f->solver != RR_SOLVER_BAND_LU) {
+    if (f->tev[2]) RR_HIP(hipEventRecord(f->tev[2], s));
+    rr_status st = krylov_solve(f, k, adjoint, Bm, bstride, X, s);
+    if (f->tev[3]) RR_HIP(hipEventRecord(f->tev[3], s));
+    return st;
+  }
   const bool mixed = f->prec == RR_MIXED;
   if (f->tev[2]) RR_HIP(hipEventRecord(f->tev[2], s));
   RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
@@ -311,6 +395,23 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
       (tune->gmres_restart < 0 || tune->gmres_restart > kGmresMaxRestart))
     return fail(RR_ERR_INVALID, "gmres_restart out of range");
   if (tune && tune->superblock > 8) return fail(RR_ERR_INVALID, "superblock must be <= 8");
+  const int solver = tune ? tune->solver : RR_SOLVER_BAND_LU;
+  if (solver != RR_SOLVER_BAND_LU && solver != RR_SOLVER_BICGSTAB && solver != RR_SOLVER_GMRES)
+    return fail(RR_ERR_INVALID, "unknown solver");
+  const bool krylov = solver != RR_SOLVER_BAND_LU;
+  if (krylov) {
+    if (prec != RR_FP64) return fail(RR_ERR_INVALID, "the Krylov solvers run in FP64 only");
+    if (tune->precond != RR_PRECOND_JACOBI && tune->precond != RR_PRECOND_ILU0)
+      return fail(RR_ERR_INVALID, "unknown preconditioner");
+    if (tune->krylov_maxit < 0 || tune->krylov_maxit > 100000)
+      return fail(RR_ERR_INVALID, "krylov_maxit out of range");
+    if (!(tune->krylov_tol >= 0.0) || tune->krylov_tol >= 1.0)
+      return fail(RR_ERR_INVALID, "krylov_tol must be in [0, 1)");
+    if (tune->gmres_restart < 0 || tune->gmres_restart > kGmresMaxRestart)
+      return fail(RR_ERR_INVALID, "gmres_restart out of range");
+    if (tune->precond == RR_PRECOND_ILU0 && ilu0_lds(p->ny) > 160 * 1024)
+      return fail(RR_ERR_INVALID, "ILU(0) holds two anti-diagonals of ny nodes in LDS: ny too large");
+  }
   if (!is_dev_ptr(p->coef) || (p->phi && !is_dev_ptr(p->phi)) || (p->U && !is_dev_ptr(p->U)))
     return fail(RR_ERR_INVALID, "coef/phi/U must be device pointers");
 
@@ -335,6 +436,12 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->refine_iters = tune && tune->refine_iters ? tune->refine_iters : 6;
   f->refine_tol = tune && tune->refine_tol > 0 ? tune->refine_tol : 1e-10;
   f->refine_tol_sketch = tune && tune->refine_tol_sketch > 0 ? tune->refine_tol_sketch : 1e-8;
+  f->solver = solver;
+  if (krylov) {
+    f->precond = tune->precond;
+    f->krylov_maxit = tune->krylov_maxit ? tune->krylov_maxit : 1000;
+    f->krylov_tol = tune->krylov_tol > 0 ? tune->krylov_tol : 1e-10;
+  }
   f->omega_host.resize(2 * n_omega);
   for (int i = 0; i < n_omega; i++) {
     f->omega_host[2 * i] = omega_re[i];
@@ -355,11 +462,22 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   if (p->phi) ALLOC(f->phi, pl.phi);
   if (p->U) ALLOC(f->U, pl.U);
   ALLOC(f->omega, pl.omega);
-  ALLOC(f->tiles, pl.tiles);
-  ALLOC(f->xs, pl.xs);
-  ALLOC(f->cbuf, pl.cbuf);
-  ALLOC(f->flags, pl.flags);
-  f->flag_count = pl.nflags;
+  if (!krylov) {  // the band LU and its dataflow state
+    ALLOC(f->tiles, pl.tiles);
+    ALLOC(f->xs, pl.xs);
+    ALLOC(f->cbuf, pl.cbuf);
+    ALLOC(f->flags, pl.flags);
+    f->flag_count = pl.nflags;
+  } else {        // the preconditioner and the Krylov vectors
+    const size_t cols = (size_t)n_omega * k_max, cplx = 2 * sizeof(double);
+    ALLOC(f->pc_dinv, (size_t)n_omega * nn * 4 * cplx);
+    const int nvec = solver == RR_SOLVER_BICGSTAB ? 7 : 1;
+    for (int v = 0; v < nvec; v++) ALLOC(f->kv[v], pl.vec);
+    ALLOC(f->kpart, cols * krylov_nchunk(n64) * 2 * cplx);
+    ALLOC(f->kscal, cols * 4 * cplx);
+    ALLOC(f->kbnorm, cols * sizeof(double));
+    ALLOC(f->kactive, cols * sizeof(uint32_t));
+  }
   ALLOC(f->ctrl, pl.ctrl);
   ALLOC(f->theta, pl.theta);
   ALLOC(f->work1, pl.vec);
@@ -377,8 +495,9 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->small.kmax = k_max;
   f->grad_nchunk = pl.grad_nchunk;
   ALLOC(f->grad_partial, pl.grad);
-  if (prec == RR_MIXED && tune && tune->refine_method == RR_REFINE_GMRES) {
-    const int m = tune->gmres_restart ? tune->gmres_restart : 8;
+  if ((prec == RR_MIXED && tune && tune->refine_method == RR_REFINE_GMRES) ||
+      solver == RR_SOLVER_GMRES) {
+    const int m = tune->gmres_restart ? tune->gmres_restart : (krylov ? kGmresMaxRestart : 8);
     const size_t cols = (size_t)n_omega * k_max, cplx = 2 * sizeof(double);
     f->gm.m = m;
     ALLOC(f->gm.V, (size_t)(m + 1) * pl.vec);
@@ -422,8 +541,8 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
     f->has_burgers = true;
   }
   {
-    hipError_t e = prepare_factor(T, prec == RR_MIXED);
-    if (e == hipSuccess) e = prepare_solve(T, prec == RR_MIXED);
+    hipError_t e = krylov ? prepare_krylov(p->ny) : prepare_factor(T, prec == RR_MIXED);
+    if (e == hipSuccess && !krylov) e = prepare_solve(T, prec == RR_MIXED);
     if (e != hipSuccess) {
       st = fail(RR_ERR_HIP, std::string("kernel attributes: ") + hipGetErrorString(e));
       goto fail_free;
@@ -444,6 +563,17 @@ fail_free:
 rr_status rr_refactor(rr_factors* f, void* stream) {
   if (!f) return fail(RR_ERR_INVALID, "NULL handle");
   if (f->sticky_hip_error) return fail(RR_ERR_HIP, "handle is unusable after a HIP error");
+  if (f->solver != RR_SOLVER_BAND_LU) {  // no LU: the preconditioner of every shift
+    if (f->tev[0]) (void)hipEventRecord(f->tev[0], (hipStream_t)stream);
+    hipError_t e = launch_pc_setup(opdesc(f), f->precond, f->omega, f->n_omega, f->pc_dinv,
+                                   st_word(f), (hipStream_t)stream);
+    if (f->tev[1]) (void)hipEventRecord(f->tev[1], (hipStream_t)stream);
+    if (e != hipSuccess) {
+      f->sticky_hip_error = true;
+      return fail(RR_ERR_HIP, std::string("preconditioner launch: ") + hipGetErrorString(e));
+    }
+    return RR_OK;
+  }
   hipError_t e = launch_factor(opdesc(f), f->geom, f->omega, f->n_omega, f->prec == RR_MIXED,
                                f->tiles, f->flags, factor_counters(f), st_word(f), f->grid,
                                (hipStream_t)stream, f->tev);
@@ -655,12 +785,22 @@ rr_status rr_check(rr_factors* f, void* stream) {
     (void)hipMemcpy(f->ctrl, &zero, sizeof(zero), hipMemcpyHostToDevice);
   }
   if (w & ST_TIMEOUT) return fail(RR_ERR_TIMEOUT, "a dataflow wait timed out");
-  if (w & ST_SINGULAR) return fail(RR_ERR_SINGULAR, "zero or non-finite pivot in the band LU");
+  if (w & ST_SINGULAR)
+    return fail(RR_ERR_SINGULAR, f->solver != RR_SOLVER_BAND_LU
+                                     ? "singular node block in the preconditioner"
+                                     : "zero or non-finite pivot in the band LU");
   if (w & ST_NONFINITE) return fail(RR_ERR_NONFINITE, "non-finite values in the results");
-  if (w & ST_BREAKDOWN) return fail(RR_ERR_BREAKDOWN, "Gram matrix not positive definite");
+  if (w & ST_BREAKDOWN)
+    return fail(RR_ERR_BREAKDOWN, f->solver == RR_SOLVER_BICGSTAB
+                                      ? "BiCGStab breakdown (a vanishing rho or <rhat, v>) or "
+                                        "a Gram matrix not positive definite"
+                                      : "Gram matrix not positive definite");
   if (w & ST_SVD_NOT_CONVERGED)
     return fail(RR_ERR_NOT_CONVERGED, "the k x k Jacobi SVD did not converge in " +
                                           std::to_string(f->small.jacobi_sweeps) + " sweeps");
+  if ((w & ST_NOT_CONVERGED) && f->solver != RR_SOLVER_BAND_LU)
+    return fail(RR_ERR_NOT_CONVERGED, "a Krylov solve missed its tolerance in " +
+                                          std::to_string(f->krylov_maxit) + " iterations");
   if (w & ST_NOT_CONVERGED) {
     std::string m = "refinement did not converge (most unconverged columns after each correction:";
     for (int it = 0; it < f->refine_iters; it++) m += " " + std::to_string(ctrl[4 + it]);
@@ -670,6 +810,16 @@ rr_status rr_check(rr_factors* f, void* stream) {
 }
 
 int32_t rr_refine_count(rr_factors* f) { return f ? f->refine_used : 0; }
+
+rr_status rr_precond_apply(rr_factors* f, int32_t k, int32_t adjoint, const double* X, double* Y,
+                           void* stream) {
+  if (!f || !X || !Y) return fail(RR_ERR_INVALID, "NULL pointer");
+  if (f->solver == RR_SOLVER_BAND_LU) return fail(RR_ERR_INVALID, "not a Krylov handle");
+  if (k < 1 || k > f->k_max) return fail(RR_ERR_INVALID, "k out of range");
+  RR_HIP(launch_pc_apply(opdesc(f), f->precond, f->n_omega, k, adjoint ? 1 : 0, f->pc_dinv, X, Y,
+                         nullptr, nullptr, (hipStream_t)stream));
+  return RR_OK;
+}
 
 rr_status rr_set_timing_events(rr_factors* f, void* factor_begin, void* factor_end,
                                void* solve_begin, void* solve_end) {

@@ -240,6 +240,37 @@ hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const doub
                                 const uint32_t* skip = nullptr);
 // Zero the measured contractions of every shift (after a refactorisation).
 hipError_t launch_refine_reset(int n_omega, double* rho, hipStream_t s);
+// LU-free Krylov solves (rr_krylov.hip)
+int krylov_nchunk(int64_t n);
+size_t ilu0_lds(int ny);
+hipError_t prepare_krylov(int ny);
+// Dinv[w][p] (4 complex): the inverted node blocks of the preconditioner
+hipError_t launch_pc_setup(const OpDesc& op, int precond, const double* omega, int n_omega,
+                           double* Dinv, uint32_t* status, hipStream_t s);
+// Y = K^-1 X (or K^-H X) for k columns of every shift; systems with
+// active[q] == 0 are left alone (active may be NULL)
+hipError_t launch_pc_apply(const OpDesc& op, int precond, int n_omega, int k, int adjoint,
+                           const double* Dinv, const double* X, double* Y,
+                           const uint32_t* active, const uint32_t* skip, hipStream_t s);
+// partial sums of <A_e, B_e> per system (npair 1 or 2)
+hipError_t launch_kdot(int64_t n, int n_omega, int k, int npair, const double* A0,
+                       const double* B0, const double* A1, const double* B1, double* partial,
+                       const uint32_t* active, const uint32_t* skip, hipStream_t s);
+// the scalar steps of BiCGStab (mode 0 start, 1 rho / beta, 2 alpha, 3 omega,
+// 4 convergence check), ks: 4 complex per system
+hipError_t launch_bicg_scalars(int N, int64_t n, int mode, int it, double tol,
+                               const double* partial, double* ks, double* bnorm2,
+                               uint32_t* active, uint32_t* conv, uint32_t* status,
+                               const uint32_t* skip, hipStream_t s);
+// vector steps: 0 p = r + beta (p - omega v); 1 r -= alpha v;
+// 2 x += alpha y + omega z, r -= omega t; 3 x += d
+hipError_t launch_bicg_vec(int which, int64_t n, int n_omega, int k, const double* ks,
+                           const double* a, const double* b, const double* c, double* x,
+                           double* y, const uint32_t* active, const uint32_t* skip,
+                           hipStream_t s);
+hipError_t launch_kcopy(int64_t count, const double* a, double* b, hipStream_t s);
+hipError_t launch_latch_live(int N, const uint32_t* active, uint32_t* status, uint32_t bit,
+                             hipStream_t s);
 // gradient kernel (rr_grad.hip)
 hipError_t launch_grad(int nx, int ny, double hx, double hy, int n_omega,
                        const double* omega, const double* sigma1, const double* u1,
@@ -260,7 +291,18 @@ struct rr_factors {
   int refine_iters;
   double refine_tol;         // projection / recovery solves
   double refine_tol_sketch;  // sketch and subspace-iteration solves
-  rr::GmresWs gm;                           // GMRES-IR (mixed only; gm.m = 0: plain)
+  rr::GmresWs gm;                           // GMRES-IR (mixed) or the Krylov GMRES
+  // LU-free solves (rr_tuning.solver != RR_SOLVER_BAND_LU)
+  int solver = RR_SOLVER_BAND_LU;
+  int precond = RR_PRECOND_JACOBI;
+  int krylov_maxit = 1000;
+  double krylov_tol = 1e-10;
+  double* pc_dinv = nullptr;     // n_omega * nx*ny * 4 complex
+  double* kv[7] = {};            // BiCGStab blocks r, rhat, p, v, y, z, t (GMRES: kv[0])
+  double* kpart = nullptr;       // dot-product partial sums
+  double* kscal = nullptr;       // per-system BiCGStab scalars
+  double* kbnorm = nullptr;      // per-system ||b||^2
+  uint32_t* kactive = nullptr;   // per-system: 1 while not converged
   rr_test_matrix tm_kind = RR_TM_GAUSSIAN;  // step 1's test matrix
   int tm_zeta = 0;
   // private copies of the problem
