@@ -218,7 +218,12 @@ rr_status rr_apply(const rr_problem* p, const double* omega_re, const double* om
 /* Factor M(omega_w) = L_w U_w (no pivoting, band kl = ku = 2*ny) for each of
  * the n_omega shifts; the factors live in the returned handle, which also
  * takes private copies of coef, phi and U.  k_max bounds the sketch width of
- * later calls (workspaces are sized for it).  omega_re / omega_im: host arrays
+ * later calls (workspaces are sized for it): 1 .. 32 in mixed precision,
+ * 1 .. 512 in FP64, where widths above 32 (the k study of Section 3.2,
+ * Fig. 7) take global-memory k x k kernels and band solves of 32 columns at
+ * a time, and a Gram matrix that is not numerically positive definite is
+ * reported as RR_ERR_BREAKDOWN instead of taking shifted CholeskyQR3.
+ * rr_resvd takes the same widths.  omega_re / omega_im: host arrays
  * of n_omega doubles (omega_im may be NULL: real shifts).  On success *out is
  * a new handle; the factorisation itself is enqueued on `stream` and its
  * device-side status is reported by rr_check. */

@@ -80,7 +80,8 @@ void free_all(rr_factors* f) {
                 f->small.Rinv, f->small.W, f->small.Ut, f->small.rho, f->small.shifted, f->grad_partial,
                 f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial,
                 f->pc_dinv, f->kv[0], f->kv[1], f->kv[2], f->kv[3], f->kv[4], f->kv[5],
-                f->kv[6], f->kpart, f->kscal, f->kbnorm, f->kactive};
+                f->kv[6], f->kpart, f->kscal, f->kbnorm, f->kactive, f->small.big1,
+                f->small.big2, f->wide_tmp};
   for (void* p : ps) {
     if (!p) continue;
     if (f->dealloc) f->dealloc(p, f->alloc_ctx);
@@ -98,6 +99,28 @@ uint32_t* conv_word(rr_factors* f) { return f->ctrl + 3; }
 uint32_t* factor_counters(rr_factors* f) { return f->ctrl + 20; }
 // ctrl[4 + it]: unconverged columns after correction it (mixed solves)
 constexpr int kMaxRefine = 16;
+// Sketch widths above this take the wide k x k kernels (rr_bigk.hip) and
+// band solves in groups of this many columns (FP64 only).
+constexpr int kNarrowK = 32;
+
+// The k x k steps for narrow (k <= 32: LDS-resident) or wide sketches.
+hipError_t cholqr(rr_factors* f, int n_omega, int k, double* Y, hipStream_t s) {
+  if (k <= kNarrowK) return launch_cholqr2(f->n, n_omega, k, Y, f->small, st_word(f), s);
+  return launch_cholqr2_big(f->n, n_omega, k, Y, f->wide_tmp, f->small, st_word(f), s);
+}
+hipError_t small_svd(rr_factors* f, int k, const double* Z, const double* Q, double* sigma,
+                     double* V, double* Uqu, hipStream_t s) {
+  if (k <= kNarrowK)
+    return launch_small_svd(f->n, f->n_omega, k, Z, Q, sigma, V, Uqu, f->small, st_word(f), s);
+  return launch_small_svd_big(f->n, f->n_omega, k, Z, Q, sigma, V, Uqu, f->wide_tmp, f->small,
+                              st_word(f), s);
+}
+hipError_t colnorm_scale(rr_factors* f, int k, const double* W, double* sigma, double* U,
+                         hipStream_t s) {
+  if (k <= kNarrowK)
+    return launch_colnorm_scale(f->n, f->n_omega, k, W, sigma, U, f->small, st_word(f), s);
+  return launch_colnorm_big(f->n, f->n_omega, k, W, sigma, U, st_word(f), s);
+}
 
 // After correction `it`: record the unconverged-column count and mark the
 // solve converged when it is zero (later corrections then skip their work).
@@ -133,7 +156,7 @@ hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStr
   };
   if (e == hipSuccess) e = solve32(r, V(0));
   if (e == hipSuccess)
-    e = launch_colnorm_scale(f->n, n_omega, k, V(0), g.beta, V(0), f->small, st_word(f), s);
+    e = colnorm_scale(f, k, V(0), g.beta, V(0), s);
   for (int j = 0; e == hipSuccess && j < m; j++) {
     e = launch_apply(opdesc(f), f->omega, n_omega, k, adjoint, V(j), nullptr, blk, g.t, s, skip);
     if (e == hipSuccess) e = solve32(g.t, V(j + 1));
@@ -141,8 +164,7 @@ hipError_t gmres_correction(rr_factors* f, int k, int adjoint, double* r, hipStr
       e = launch_gs_project(f->n, n_omega, k, j, g, V(j + 1), skip, s);
     double* nrm = g.h;  // free until the next projection
     if (e == hipSuccess)
-      e = launch_colnorm_scale(f->n, n_omega, k, V(j + 1), nrm, V(j + 1), f->small, st_word(f),
-                               s);
+      e = colnorm_scale(f, k, V(j + 1), nrm, V(j + 1), s);
     if (e == hipSuccess) e = launch_store_subdiag(n_omega, k, j, g, nrm, skip, s);
   }
   if (e == hipSuccess) e = launch_gmres_finish(f->n, n_omega, k, g, r, skip, s);
@@ -233,6 +255,21 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
     if (f->tev[3]) RR_HIP(hipEventRecord(f->tev[3], s));
     return st;
   }
+  if (k > kNarrowK) {
+    // a wide block (FP64 only): the band solve takes 32 columns at a time,
+    // gathered into and scattered from two narrow blocks
+    double* nb = f->wide_tmp;
+    double* nx = f->wide_tmp + 2 * (size_t)f->n_omega * kNarrowK * f->n;
+    for (int c0 = 0; c0 < k; c0 += kNarrowK) {
+      const int kg = std::min(kNarrowK, k - c0);
+      RR_HIP(launch_cols_copy(f->n, f->n_omega, k, bstride, c0, kg, Bm, nb, true, s));
+      RR_HIP(launch_solve(f->geom, f->n, f->n_omega, kg, false, f->tiles, adjoint, nb,
+                          (int64_t)kg * f->n, nx, f->xs, f->cbuf, f->flags, ticket_word(f),
+                          st_word(f), f->solve_grid, s));
+      RR_HIP(launch_cols_copy(f->n, f->n_omega, k, (int64_t)k * f->n, c0, kg, nx, X, false, s));
+    }
+    return RR_OK;
+  }
   const bool mixed = f->prec == RR_MIXED;
   if (f->tev[2]) RR_HIP(hipEventRecord(f->tev[2], s));
   RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
@@ -269,12 +306,12 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
 struct Plan {
   BandGeom geom;
   size_t coef, phi, U, omega, tiles, xs, cbuf, flags, ctrl, theta, vec, work3, partial, kk2, rho,
-      shifted, grad;
+      shifted, grad, big = 0, wide = 0;
   int nchunk, grad_nchunk;
   size_t nflags;
   size_t total() const {
     return coef + phi + U + omega + tiles + xs + cbuf + flags + ctrl + theta + 2 * vec + work3 +
-           partial + 5 * kk2 + rho + shifted + grad;
+           partial + 5 * kk2 + rho + shifted + grad + 2 * big + wide;
   }
 };
 
@@ -302,8 +339,9 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   pl.U = has_U ? (size_t)(nx + 2) * (ny + 2) * sizeof(double) : 0;
   pl.omega = 2 * (size_t)n_omega * sizeof(double);
   pl.tiles = (size_t)n_omega * pl.geom.tiles_per_omega() * T * T * elem;
-  pl.xs = (size_t)n_omega * pl.geom.NB * T * solve_np(k_max) * 2 * sizeof(double);
-  pl.cbuf = (size_t)n_omega * std::max(pl.geom.P, 1) * T * solve_np(k_max) * 2 * sizeof(double);
+  const int kn = std::min(k_max, kNarrowK);  // widest solve launch
+  pl.xs = (size_t)n_omega * pl.geom.NB * T * solve_np(kn) * 2 * sizeof(double);
+  pl.cbuf = (size_t)n_omega * std::max(pl.geom.P, 1) * T * solve_np(kn) * 2 * sizeof(double);
   pl.nflags = std::max({(size_t)n_omega * pl.geom.tiles_per_omega(), (size_t)n_omega * pl.geom.NB,
                         (size_t)ssolve_counters(pl.geom, n_omega)});
   pl.flags = pl.nflags * sizeof(int);
@@ -313,7 +351,14 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   pl.work3 = prec == RR_MIXED ? pl.vec : 0;
   pl.nchunk = (int)((n + 2047) / 2048);
   const size_t kk = (size_t)std::max(k_max * k_max, 64);
-  pl.partial = (size_t)n_omega * pl.nchunk * kk * 2 * sizeof(double);
+  const size_t kkn = (size_t)std::max(kn * kn, 64);
+  pl.partial = (size_t)n_omega * std::max<size_t>(pl.nchunk * kkn,
+                                                  k_max > kNarrowK ? gramb_chunks(n) * kk : 0) *
+               2 * sizeof(double);
+  if (k_max > kNarrowK) {  // the wide k x k steps' scratch and one wide block
+    pl.big = (size_t)n_omega * (k_max + 1) * (k_max + 1) * 2 * sizeof(double);
+    pl.wide = (size_t)n_omega * std::max(k_max, 2 * kNarrowK) * n * 2 * sizeof(double);
+  }
   pl.kk2 = (size_t)n_omega * kk * 2 * sizeof(double);
   pl.rho = prec == RR_MIXED ? (size_t)n_omega * kRhoStride * sizeof(double) : 0;
   pl.shifted = (size_t)n_omega * sizeof(uint32_t);
@@ -328,6 +373,8 @@ rr_status check_k(const rr_factors* f, int k) {
   if (k < 1 || k > f->k_max) return fail(RR_ERR_INVALID, "k must be in [1, k_max]");
   return RR_OK;
 }
+
+
 
 }  // namespace
 
@@ -377,8 +424,10 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   if (!p || !p->coef || !omega_re) return fail(RR_ERR_INVALID, "NULL pointer");
   if (p->nx < 1 || p->ny < 1) return fail(RR_ERR_INVALID, "nx, ny must be >= 1");
   if (n_omega < 1) return fail(RR_ERR_INVALID, "n_omega must be >= 1");
-  if (k_max < 1 || k_max > 32) return fail(RR_ERR_INVALID, "k_max must be in [1, 32]");
   if (prec != RR_FP64 && prec != RR_MIXED) return fail(RR_ERR_INVALID, "unknown precision");
+  if (k_max < 1 || k_max > (prec == RR_FP64 ? kMaxWideK : kNarrowK))
+    return fail(RR_ERR_INVALID, prec == RR_FP64 ? "k_max must be in [1, 512]"
+                                                : "k_max must be in [1, 32] in mixed precision");
   int64_t n64 = 2 * (int64_t)p->nx * p->ny;
   if (n64 > (1ll << 30)) return fail(RR_ERR_INVALID, "operator too large");
   if (k_max > n64) return fail(RR_ERR_INVALID, "k_max exceeds n");
@@ -491,6 +540,11 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   ALLOC(f->small.Ut, pl.kk2);
   if (prec == RR_MIXED) ALLOC(f->small.rho, pl.rho);
   ALLOC(f->small.shifted, pl.shifted);
+  if (k_max > kNarrowK) {
+    ALLOC(f->small.big1, pl.big);
+    ALLOC(f->small.big2, pl.big);
+    ALLOC(f->wide_tmp, pl.wide);
+  }
   f->small.nchunk = pl.nchunk;
   f->small.kmax = k_max;
   f->grad_nchunk = pl.grad_nchunk;
@@ -600,18 +654,18 @@ rr_status rr_sketch_solve(rr_factors* f, int32_t k, uint64_t seed, int32_t power
     const int z = f->tm_zeta <= 0 ? std::min(k, 8) : std::min<int>(f->tm_zeta, k);
     RR_HIP(launch_sketch(opdesc(f), f->phi, k, seed, f->tm_kind, z, f->theta, s));
     if (f->tm_kind == RR_TM_ORTHONORMAL) {  // orthonormal columns, then eq. 10's weights
-      RR_HIP(launch_cholqr2(f->n, 1, k, f->theta, f->small, st_word(f), s));
+      RR_HIP(cholqr(f, 1, k, f->theta, s));
       if (f->phi) RR_HIP(launch_weight_rows(f->n, k, f->phi, f->theta, s));
     }
   }
   const double ts = f->refine_tol_sketch;
   if ((st = solve_any(f, k, 0, f->theta, 0, Q, ts, s)) != RR_OK) return st;         // step 2
-  RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, f->small, st_word(f), s));       // step 3
+  RR_HIP(cholqr(f, f->n_omega, k, Q, s));                                          // step 3
   for (int it = 0; it < power_iters; it++) {                                        // 2.2.1
     if ((st = solve_any(f, k, 1, Q, blk, f->work1, ts, s)) != RR_OK) return st;
-    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, f->work1, f->small, st_word(f), s));
+    RR_HIP(cholqr(f, f->n_omega, k, f->work1, s));
     if ((st = solve_any(f, k, 0, f->work1, blk, Q, ts, s)) != RR_OK) return st;
-    RR_HIP(launch_cholqr2(f->n, f->n_omega, k, Q, f->small, st_word(f), s));
+    RR_HIP(cholqr(f, f->n_omega, k, Q, s));
   }
   return RR_OK;
 }
@@ -657,13 +711,12 @@ rr_status rr_gains(rr_factors* f, int32_t k, const double* Q, const double* Z, r
     return fail(RR_ERR_INVALID, "outputs may not alias inputs");
   hipStream_t s = (hipStream_t)stream;
   // step 5 (and eq. 8 when asked)
-  RR_HIP(launch_small_svd(f->n, f->n_omega, k, Z, Q, sigma_B, V,
-                          mode == RR_RESP_QU ? Uresp : nullptr, f->small, st_word(f), s));
+  RR_HIP(small_svd(f, k, Z, Q, sigma_B, V, mode == RR_RESP_QU ? Uresp : nullptr, s));
   if (mode == RR_RESP_AV) {
     // steps 6-9: W = M^-1 V, sigma_j = ||W_j||, u_j = W_j / sigma_j
     double* W = Uresp ? Uresp : f->work2;
     if ((st = solve_any(f, k, 0, V, (int64_t)k * f->n, W, f->refine_tol, s)) != RR_OK) return st;
-    RR_HIP(launch_colnorm_scale(f->n, f->n_omega, k, W, sigma_AV, Uresp, f->small, st_word(f), s));
+    RR_HIP(colnorm_scale(f, k, W, sigma_AV, Uresp, s));
   }
   return RR_OK;
 }
@@ -683,7 +736,7 @@ rr_status rr_resvd(rr_factors* f, int32_t k, const double* Us, const double* sca
   }
   // step 10: U^Sigma = Qz R, R^H = Ut S W^H, so U^Sigma = (Qz W) S Ut^H: the
   // left singular vectors are Qz W and the right ones Ut; step 11: V <- V Ut
-  RR_HIP(launch_small_svd(f->n, f->n_omega, k, X, V, sigma, U, Vnew, f->small, st_word(f), s));
+  RR_HIP(small_svd(f, k, X, V, sigma, U, Vnew, s));
   return RR_OK;
 }
 
@@ -858,7 +911,8 @@ rr_status rr_set_allocator(rr_alloc_fn alloc, rr_free_fn dealloc, void* ctx) {
 
 size_t rr_factor_bytes(int32_t nx, int32_t ny, int32_t n_omega, int32_t k_max, rr_precision prec,
                        int32_t tile) {
-  if (nx < 1 || ny < 1 || n_omega < 1 || k_max < 1 || k_max > 32) return 0;
+  if (nx < 1 || ny < 1 || n_omega < 1 || k_max < 1) return 0;
+  if (k_max > (prec == RR_FP64 ? kMaxWideK : kNarrowK)) return 0;
   const int T = tile ? tile : 64;
   if (T != 32 && T != 64) return 0;
   return make_plan(nx, ny, n_omega, k_max, prec, T, true, true, 0).total();

@@ -185,6 +185,8 @@ struct SmallWs {   // workspace for tall-skinny reductions
   int nchunk;
   int kmax;
   int jacobi_sweeps = kJacobiSweeps;  // sweep cap of the k x k Jacobi SVD
+  double* big1 = nullptr;  // wide sketches (k > 32): n_omega * (kmax+1)^2 complex each
+  double* big2 = nullptr;
 };
 // CholQR2 in place: Y <- Q = Y R^-1 with R upper, real positive diagonal.
 // A shift whose Gram matrix is not numerically positive definite takes
@@ -240,6 +242,21 @@ hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const doub
                                 const uint32_t* skip = nullptr);
 // Zero the measured contractions of every shift (after a refactorisation).
 hipError_t launch_refine_reset(int n_omega, double* rho, hipStream_t s);
+// Wide sketches, 32 < k <= kMaxWideK (rr_bigk.hip), FP64 only
+constexpr int kMaxWideK = 512;
+int gramb_chunks(int64_t n);
+hipError_t launch_cholqr2_big(int64_t n, int n_omega, int k, double* Y, double* tmp, SmallWs& ws,
+                              uint32_t* status, hipStream_t s);
+hipError_t launch_small_svd_big(int64_t n, int n_omega, int k, const double* Z, const double* Q,
+                                double* sigma, double* V, double* Uqu, double* tmp,
+                                SmallWs& ws, uint32_t* status, hipStream_t s);
+hipError_t launch_colnorm_big(int64_t n, int n_omega, int k, const double* X, double* sigma,
+                              double* U, uint32_t* status, hipStream_t s);
+// columns [c0, c0 + kg) of a block with k columns per shift (shift stride
+// wstride complex, 0 = shared) to / from a block of kg columns per shift
+hipError_t launch_cols_copy(int64_t n, int n_omega, int k, int64_t wstride, int c0, int kg,
+                            const double* src, double* dst, bool gather, hipStream_t s);
+
 // LU-free Krylov solves (rr_krylov.hip)
 int krylov_nchunk(int64_t n);
 size_t ilu0_lds(int ny);
@@ -300,6 +317,7 @@ struct rr_factors {
   double* pc_dinv = nullptr;     // n_omega * nx*ny * 4 complex
   double* kv[7] = {};            // BiCGStab blocks r, rhat, p, v, y, z, t (GMRES: kv[0])
   double* kpart = nullptr;       // dot-product partial sums
+  double* wide_tmp = nullptr;    // k_max > 32: n_omega * max(k_max, 64) * n complex
   double* kscal = nullptr;       // per-system BiCGStab scalars
   double* kbnorm = nullptr;      // per-system ||b||^2
   uint32_t* kactive = nullptr;   // per-system: 1 while not converged

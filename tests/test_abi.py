@@ -102,7 +102,10 @@ def test_sweep_entry_points_reject_bad_arguments_on_host():
 def test_factor_bytes_matches_the_layout():
     L = _lib.lib()
     assert L.rr_factor_bytes(0, 4, 1, 4, 0, 0) == 0
-    assert L.rr_factor_bytes(4, 4, 1, 33, 0, 0) == 0
+    assert L.rr_factor_bytes(4, 4, 1, 33, 1, 0) == 0    # mixed precision: k_max <= 32
+    assert L.rr_factor_bytes(4, 4, 1, 513, 0, 0) == 0   # FP64: k_max <= 512
+    # a wide FP64 sketch adds its k x k scratch and one wide block
+    assert L.rr_factor_bytes(4, 4, 1, 33, 0, 0) > L.rr_factor_bytes(4, 4, 1, 32, 0, 0)
     assert L.rr_factor_bytes(4, 4, 1, 4, 0, 48) == 0
     nx, ny, nw, k, T = 512, 256, 16, 20, 64
     n, b = 2 * nx * ny, 2 * ny
