@@ -117,7 +117,8 @@ typedef struct {
 /* Tuning knobs; pass NULL to rr_factor for defaults (or the autotuner's pick). */
 typedef struct {
   int32_t tile;          /* band tile edge T: 32 or 64 (default 64)             */
-  int32_t grid;          /* persistent workgroups per launch; 0 = 2 per CU      */
+  int32_t grid;          /* persistent workgroups of the factorisation; 0 = 2
+                            per CU (the solves use at least 2 per CU)          */
   int32_t refine_iters;  /* mixed only: most corrections per solve (default 6,
                             at most 16).  The launches are fixed (graph-safe)
                             but skip their work on the device once every

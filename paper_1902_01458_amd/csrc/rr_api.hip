@@ -481,7 +481,9 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   f->geom.NB = (f->n + T - 1) / T;
   f->geom.P = superblock_tiles(tune ? tune->superblock : 0, T, f->geom.B);
   f->grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
-  f->solve_grid = tune && tune->grid > 0 ? tune->grid : 2 * device_cus();
+  // the solves' persistent workgroups queue behind the resident ones, so a
+  // grid of two per CU never idles a CU that could hold two
+  f->solve_grid = std::max(tune && tune->grid > 0 ? tune->grid : 0, 2 * device_cus());
   f->refine_iters = tune && tune->refine_iters ? tune->refine_iters : 6;
   f->refine_tol = tune && tune->refine_tol > 0 ? tune->refine_tol : 1e-10;
   f->refine_tol_sketch = tune && tune->refine_tol_sketch > 0 ? tune->refine_tol_sketch : 1e-8;
