@@ -126,9 +126,10 @@ typedef struct {
   double  refine_tol;    /* mixed only: a column has converged when its last
                             correction d_j has e_j = ||d_j|| / ||x_j|| <= tol,
                             or when the error it leaves, estimated as e_j
-                            times the contraction per correction (e_j after
-                            the first correction, e_j / e_j,previous after
-                            later ones), is at most tol / 2; for the
+                            times the contraction per correction (the ratio
+                            of two successive corrections, this solve's or the
+                            largest kept per shift and direction since the
+                            factorisation), is at most tol / 2; for the
                             projection (step 4) and recovery (step 6) solves
                             (default 1e-10)                                     */
   double  refine_tol_sketch; /* mixed only: the same test for the sketch and
