@@ -26,10 +26,14 @@
 // and finishes whatever the residency or the spread over XCDs.
 // A phase's pieces count themselves done on a per-(shift, sweep, superblock,
 // phase) counter; phase A waits for the previous superblock's phase B (which
-// implies every earlier step), phase B for its own phase A.  Data handed
-// between workgroups (c and the sweep's blocks) is stored device-coherent
-// (st_coherent) before the release and the counter increment; readers poll
-// with atomics, then acquire.
+// implies every earlier step), phase B for its own phase A.  In its home team
+// a workgroup takes its next ticket while it waits for the current piece and
+// loads that piece's factor tile during the current products, so that a step
+// finds the operands of its pieces in registers.  Data handed between
+// workgroups (c and the sweep's blocks) is stored device-coherent
+// (st_coherent, written through); the counter is incremented once those
+// stores have completed, and readers poll it (four polls in flight), then
+// acquire.
 #include "rr_mfma.h"
 
 namespace rr {
@@ -38,16 +42,14 @@ namespace {
 
 enum { SM_NONE = 0, SM_UNIT_LOWER = 1, SM_UPPER = 2 };
 
-// A piece's products are walked in chunks of QC k-steps (4 QC columns of the
-// inner dimension of one tile): the A-role fragment of the stored tile and
-// the B-role fragments of the solved block for each of the NCB column
-// blocks.  With one column block in FP32 a chunk is a whole tile, so that
-// every load of a wave's tile is in flight before its first MFMA; otherwise
-// (more registers per chunk) a chunk is a half (FP32) or a quarter (FP64) of
-// a tile and the next chunk is loaded one ahead of the current one's MFMAs
-// (two buffers).
+// A long piece (more inner tiles than waves, e.g. a half-band of many tiles)
+// walks its tiles in chunks of QC k-steps (4 QC columns of the inner
+// dimension of one tile, a quarter of a tile): the A-role fragment of the
+// stored tile and the B-role fragments of the solved block for each of the
+// NCB column blocks, the next chunk loaded one ahead of the current one's
+// MFMAs (two buffers).  Short pieces (below) hold a whole tile instead.
 template <typename R, int T, int NCB>
-constexpr int ss_qc() { return sizeof(R) == 8 ? T / 16 : (NCB == 1 ? T / 4 : T / 8); }
+constexpr int ss_qc() { return T / 16; }
 
 template <typename R, int T, int NCB>
 struct SChunk {
@@ -160,35 +162,55 @@ __device__ __forceinline__ int xcc_id() {
   return (int)(__builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xF);
 }
 
-// Thread 0 polls *c until it reaches `want`, then issues one acquire fence;
-// the barrier hands the result to every wave.  Bounded like every dataflow
-// wait of the library (ST_TIMEOUT).
-__device__ __forceinline__ void ss_wait(int* c, int want, uint32_t* status) {
+// Thread 0 optionally takes the next ticket of counter `tk` (its atomic in
+// flight while it polls) and polls *c until it reaches `want`, with four
+// polls in flight so that a completed step is seen about a quarter of a
+// round trip sooner than with one; then one acquire fence.  The barrier hands
+// both to every wave.  Bounded like every dataflow wait of the library
+// (ST_TIMEOUT).  Returns the ticket, or -1 when `tk` is null.
+__device__ __forceinline__ int64_t ss_wait(int* c, int want, uint32_t* status, uint32_t* tk,
+                                           uint32_t* slot) {
   if (threadIdx.x == 0) {
-    bool live =
-        !(__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT);
-    const uint64_t t0 = wall_clock64();
-    uint32_t polls = 0;
-    while (live &&
-           __hip_atomic_fetch_add(c, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++polls > kWaitPolls || wall_clock64() - t0 > kWaitTicks) {
-        latch(status, ST_TIMEOUT);
-        live = false;
+    uint32_t t = 0;
+    if (tk) t = atomicAdd(tk, 1u);
+    if (c) {
+      if (!(__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT)) {
+        auto poll = [&]() { return __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+        int v0 = poll(), v1 = poll(), v2 = poll(), v3 = poll();
+        const uint64_t t0 = wall_clock64();
+        for (uint32_t rounds = 0;; rounds++) {
+          if (v0 >= want) break;
+          v0 = poll();
+          if (v1 >= want) break;
+          v1 = poll();
+          if (v2 >= want) break;
+          v2 = poll();
+          if (v3 >= want) break;
+          v3 = poll();
+          if (rounds > kWaitPolls || wall_clock64() - t0 > kWaitTicks) {
+            latch(status, ST_TIMEOUT);
+            break;
+          }
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tk) *slot = t;
   }
   __syncthreads();
+  return tk ? (int64_t)__builtin_amdgcn_readfirstlane(*slot) : -1;
 }
 
-// Every thread's stores are complete, then thread 0 releases and counts the
-// piece done; barriers close the interval on both sides.
+// Every thread's stores are complete, then thread 0 counts the piece done.
+// Everything a piece hands over is stored device-coherent (st_coherent,
+// written through), so waiting for the stores is the whole release: no L2
+// write-back is needed before the count.  Barriers close the interval on
+// both sides.
 __device__ __forceinline__ void ss_done(int* c) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __hip_atomic_fetch_add(c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
@@ -197,191 +219,337 @@ __device__ __forceinline__ void ss_done(int* c) {
 constexpr int kSsWaves = 8;  // waves per workgroup: they split a piece's inner dimension
 
 template <typename R, int T, int NP>
-constexpr size_t ssolve_lds() {  // per-wave partial sums, the summed piece, its b
-  return sizeof(cplx<R>) * (size_t)16 * NP * (kSsWaves + 1) + sizeof(double2) * 16 * NP;
+constexpr size_t ssolve_lds() {  // the waves' partial sums of a piece
+  return sizeof(cplx<R>) * (size_t)16 * NP * kSsWaves;
+}
+
+// One piece: 16 rows (row block rb of tile row i of superblock S) of one
+// phase of one sweep of shift w, and the tiles lo .. hi of its inner
+// dimension (band tiles outside the superblock in phase A, the superblock's
+// inverse in phase B).
+struct SPiece {
+  int w, phase, second, S, i, rb, s0, s, lo, hi;
+};
+
+__device__ __forceinline__ SPiece ss_decode(int64_t t, int team, int teams, int nw, int npc,
+                                            int rpt, const BandGeom& g) {
+  SPiece p;
+  const int NS = g.NS(), PS = g.P, NB = g.NB, B = g.B;
+  const int pc = (int)(t % npc);
+  t /= npc;
+  p.w = team + teams * (int)(t % nw);
+  t /= nw;
+  p.phase = (int)(t % 2);
+  t /= 2;
+  const int si = (int)(t % NS);
+  p.second = (int)(t / NS);
+  p.S = p.second ? NS - 1 - si : si;
+  p.i = pc / rpt;
+  p.rb = pc % rpt;
+  p.s0 = p.S * PS;
+  p.s = p.s0 + p.i;
+  p.lo = 0;
+  p.hi = -1;
+  if (p.s < NB) {
+    if (p.phase == 0) {
+      if (!p.second) { p.lo = max(0, p.s - B); p.hi = p.s0 - 1; }
+      else { p.lo = p.s0 + PS; p.hi = min(NB - 1, p.s + B); }
+    } else {
+      if (!p.second) { p.lo = 0; p.hi = p.i; }
+      else { p.lo = p.i; p.hi = min(PS - 1, NB - 1 - p.s0); }
+    }
+  }
+  return p;
+}
+
+// The stored tile that is the A-role operand of inner index x of piece p, its
+// mask and whether it is stored row-major.
+template <typename R, int T, bool ADJ>
+__device__ __forceinline__ const cplx<R>* ss_operand(const SSolveParams& P, const SPiece& p, int x,
+                                                     int& mask, bool& xt) {
+  const int B = P.g.B, NB = P.g.NB, RT = P.g.row_tiles();
+  const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)p.w * NB * RT * (T * T);
+  auto tile = [&](int r, int c) { return tw + ((int64_t)r * RT + (c - r + B)) * (T * T); };
+  auto sbt = [&](int r, int slot) { return tw + ((int64_t)r * RT + P.g.sb_index(slot)) * (T * T); };
+  if (p.phase == 0) {
+    mask = SM_NONE;
+    xt = ADJ != (bool)p.second;  // U tiles (row-major) in this sweep
+    return ADJ ? tile(x, p.s) : tile(p.s, x);
+  }
+  const int j = x, i = p.i;
+  if (!ADJ) {
+    mask = j == i ? (p.second ? SM_UPPER : SM_UNIT_LOWER) : SM_NONE;
+    xt = p.second && j != i;  // (U-hat^-1)_ij row-major, (L-hat^-1)_ij column-major
+    return j == i ? tile(p.s, p.s) : sbt(p.s, sb_slot(i, j));
+  }
+  mask = j == i ? (p.second ? SM_UNIT_LOWER : SM_UPPER) : SM_NONE;
+  xt = !p.second && j != i;   // ((U-hat^-1)_ji)^H or ((L-hat^-1)_ji)^H
+  return j == i ? tile(p.s, p.s) : sbt(p.s0 + j, sb_slot(j, i));
+}
+
+// A piece is "short" when its inner dimension has at most one tile per wave
+// (every piece of the benchmark's band with T = 64).  A short piece's wave
+// loads the A-role values of its tile before the piece's wait, PQ of the T/4
+// k-steps (all of them in FP32, a quarter in FP64, where the rest follows in
+// chunks of PQ k-steps loaded one ahead), raw: masks are applied after the
+// wait so that no load is awaited before it.
+template <typename R, int T>
+constexpr int ss_pq() { return sizeof(R) == 8 ? T / 16 : T / 4; }
+
+template <typename R, int T>
+struct SPre {
+  cplx<R> a[ss_pq<R, T>()];
+};
+
+template <typename R, int T, bool CT, int N>
+__device__ __forceinline__ void ss_load_a(cplx<R>* a, const cplx<R>* X, int rb, bool xt, int q0) {
+  const int l = threadIdx.x & 63;
+  const int i = 16 * rb + (l & 15);
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    const int k = 4 * (q0 + q) + (l >> 4);
+    const int r = CT ? k : i, c = CT ? i : k;
+    a[q] = X[xt ? r * T + c : c * T + r];
+  }
+}
+
+template <typename R, bool CT, int N>
+__device__ __forceinline__ void ss_mask_a(cplx<R>* a, int mask, int rb, int q0) {
+  if (mask == SM_NONE) return;
+  const int l = threadIdx.x & 63;
+  const int i = 16 * rb + (l & 15);
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    const int k = 4 * (q0 + q) + (l >> 4);
+    const int r = CT ? k : i, c = CT ? i : k;
+    if (mask == SM_UNIT_LOWER && r <= c) a[q] = cplx<R>{r == c ? (R)1 : (R)0, (R)0};
+    if (mask == SM_UPPER && r > c) a[q] = cplx<R>{(R)0, (R)0};
+  }
+}
+
+template <typename R, int NP, int NCB, int N>
+__device__ __forceinline__ void ss_load_b(cplx<R> (*b)[N], const cplx<R>* V, int q0) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int cb = 0; cb < NCB; cb++)
+#pragma unroll
+    for (int q = 0; q < N; q++) b[cb][q] = V[(4 * (q0 + q) + (l >> 4)) * NP + 16 * cb + (l & 15)];
+}
+
+template <typename R, int NCB, int N, bool CA>
+__device__ __forceinline__ void ss_mma(SAcc<R, NCB>& acc, const cplx<R>* a, const cplx<R> (*b)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; q++) {
+    const R ar = a[q].re, ai = CA ? -a[q].im : a[q].im;
+    const R sa = ar + ai;
+#pragma unroll
+    for (int cb = 0; cb < NCB; cb++) {
+      const R br = b[cb][q].re, bi = b[cb][q].im;
+      acc.p1[cb] = Mf<R>::op(ar, br, acc.p1[cb]);
+      acc.p2[cb] = Mf<R>::op(ai, bi, acc.p2[cb]);
+      acc.p3[cb] = Mf<R>::op(sa, br + bi, acc.p3[cb]);
+    }
+  }
+}
+
+// The products of a short piece's wave: its tile X (A role, chunk 0 already
+// in pre) against the solved block V.
+template <typename R, int T, int NP, bool CA>
+__device__ __forceinline__ void ss_short(SAcc<R, NP / 16>& acc, SPre<R, T>& pre,
+                                         const cplx<R>* X, const cplx<R>* V, int mask, int rb,
+                                         bool xt) {
+  constexpr int NCB = NP / 16, PQ = ss_pq<R, T>(), NCK = (T / 4) / PQ;
+  cplx<R> ba[NCB][PQ];
+  ss_load_b<R, NP, NCB, PQ>(ba, V, 0);
+  if constexpr (NCK == 1) {
+    ss_mask_a<R, CA, PQ>(pre.a, mask, rb, 0);
+    ss_mma<R, NCB, PQ, CA>(acc, pre.a, ba);
+  } else {
+    cplx<R> aa[PQ], ab[PQ], bb[NCB][PQ];
+    ss_load_a<R, T, CA, PQ>(ab, X, rb, xt, PQ);
+    ss_load_b<R, NP, NCB, PQ>(bb, V, PQ);
+    ss_mask_a<R, CA, PQ>(pre.a, mask, rb, 0);
+    ss_mma<R, NCB, PQ, CA>(acc, pre.a, ba);
+#pragma unroll
+    for (int c = 1; c < NCK; c++) {
+      if (c % 2 == 1) {
+        if (c + 1 < NCK) {
+          ss_load_a<R, T, CA, PQ>(aa, X, rb, xt, (c + 1) * PQ);
+          ss_load_b<R, NP, NCB, PQ>(ba, V, (c + 1) * PQ);
+        }
+        ss_mask_a<R, CA, PQ>(ab, mask, rb, c * PQ);
+        ss_mma<R, NCB, PQ, CA>(acc, ab, bb);
+      } else {
+        if (c + 1 < NCK) {
+          ss_load_a<R, T, CA, PQ>(ab, X, rb, xt, (c + 1) * PQ);
+          ss_load_b<R, NP, NCB, PQ>(bb, V, (c + 1) * PQ);
+        }
+        ss_mask_a<R, CA, PQ>(aa, mask, rb, c * PQ);
+        ss_mma<R, NCB, PQ, CA>(acc, aa, ba);
+      }
+    }
+  }
+}
+
+template <typename R, int T, bool ADJ>
+__device__ __forceinline__ void ss_prefetch(SPre<R, T>& pre, const SSolveParams& P, const SPiece& p,
+                                            int wave) {
+  const int x = p.lo + wave;
+  if (p.hi - p.lo + 1 > kSsWaves || x > p.hi) return;
+  int mask;
+  bool xt;
+  const cplx<R>* X = ss_operand<R, T, ADJ>(P, p, x, mask, xt);
+  ss_load_a<R, T, ADJ, ss_pq<R, T>()>(pre.a, X, p.rb, xt, 0);
 }
 
 template <typename R, int T, int NP, bool ADJ>
 __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
   if (P.skip && __hip_atomic_load(P.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   constexpr int NCB = NP / 16;
-  constexpr int NT = 64 * kSsWaves;
   constexpr int RPT = T / 16;  // 16-row blocks per tile
+  constexpr int QA = T / 4;    // k-steps per tile
+  static_assert(16 * NP <= 64 * kSsWaves, "one element of a piece per thread");
   extern __shared__ __align__(16) char ss_smem[];
-  cplx<R>* red = reinterpret_cast<cplx<R>*>(ss_smem);   // [kSsWaves][16][NP]
-  cplx<R>* outb = red + kSsWaves * 16 * NP;              // [16][NP]
-  double2* bin = reinterpret_cast<double2*>(outb + 16 * NP);  // [16][NP] right-hand side
-  __shared__ uint32_t s_ticket;
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int B = P.g.B, NB = P.g.NB, RT = P.g.row_tiles(), PS = P.g.P, NS = P.g.NS();
-  const int npc = PS * RPT;  // pieces per superblock phase
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(ss_smem);  // [kSsWaves][16][NP]
+  __shared__ uint32_t s_ticket, s_next;
+  // wave-uniform, so that the tile and block pointers live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int NB = P.g.NB, NS = P.g.NS();
+  const int npc = P.g.P * RPT;  // pieces per superblock phase
   const int home = xcc_id() % P.teams;
   for (int tt = 0; tt < P.teams; tt++) {
-   const int team = (home + tt) % P.teams;
-   const int nw = (P.n_omega - team + P.teams - 1) / P.teams;  // this team's shifts
-   const int64_t total = (int64_t)2 * NS * 2 * nw * npc;
-   for (;;) {
-    const int64_t ticket = wg_ticket(P.tickets + team, &s_ticket);
-    if (ticket >= total) break;
-    int64_t t = ticket;
-    const int pc = (int)(t % npc);
-    t /= npc;
-    const int w = team + P.teams * (int)(t % nw);
-    t /= nw;
-    const int phase = (int)(t % 2);
-    t /= 2;
-    const int si = (int)(t % NS);
-    const int second = (int)(t / NS);
-    const int S = second ? NS - 1 - si : si;
-    const int i = pc / RPT, rb = pc % RPT;
-    const int s0 = S * PS, s = s0 + i;
-    int* cnt_w = P.cnt + (int64_t)w * 2 * NS * 2;
-    auto counter = [&](int sw, int sup, int ph) { return cnt_w + ((int64_t)sw * NS + sup) * 2 + ph; };
-    const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(P.tiles) + (int64_t)w * NB * RT * (T * T);
-    auto tile = [&](int r, int c) { return tw + ((int64_t)r * RT + (c - r + B)) * (T * T); };
-    auto sbt = [&](int r, int slot) {
-      return tw + ((int64_t)r * RT + P.g.sb_index(slot)) * (T * T);
-    };
-    cplx<R>* xw = reinterpret_cast<cplx<R>*>(P.xs) + (int64_t)w * NB * T * NP;
-    cplx<R>* cw = reinterpret_cast<cplx<R>*>(P.cb) + (int64_t)w * PS * T * NP;
-    // this piece's inner dimension: tiles t0 .. t1 of the band outside the
-    // superblock (phase A), or j0 .. j1 of the superblock's inverse (phase B)
-    int lo = 0, hi = -1;
-    if (s < NB) {
-      if (phase == 0) {
-        if (!second) { lo = max(0, s - B); hi = s0 - 1; }
-        else { lo = s0 + PS; hi = min(NB - 1, s + B); }
-      } else {
-        if (!second) { lo = 0; hi = i; }
-        else { lo = i; hi = min(PS - 1, NB - 1 - s0); }
+    const int team = (home + tt) % P.teams;
+    const int nw = (P.n_omega - team + P.teams - 1) / P.teams;  // this team's shifts
+    const int64_t total = (int64_t)2 * NS * 2 * nw * npc;
+    uint32_t* tick = P.tickets + team;
+    // In its home team a workgroup holds two tickets: the piece it works on
+    // and the next, whose wait it will meet with the operand already loaded.
+    // It still finishes its tickets in order, so the smallest unfinished
+    // ticket of a team is always a workgroup's current piece, whose inputs
+    // are smaller tickets, all finished.  Serving another team (after its
+    // own ran out) it takes one ticket at a time, as a piece of that team
+    // then never waits on a ticket held back behind a piece of another team.
+    const bool ahead = tt == 0;
+    int64_t cur = wg_ticket(tick, &s_ticket);
+    SPiece pc = ss_decode(cur, team, P.teams, nw, npc, RPT, P.g);
+    SPre<R, T> pre;
+    if (cur < total) ss_prefetch<R, T, ADJ>(pre, P, pc, wave);
+    while (cur < total) {
+      int* cnt_w = P.cnt + (int64_t)pc.w * 2 * NS * 2;
+      auto counter = [&](int sw, int sup, int ph) { return cnt_w + ((int64_t)sw * NS + sup) * 2 + ph; };
+      cplx<R>* xw = reinterpret_cast<cplx<R>*>(P.xs) + (int64_t)pc.w * NB * T * NP;
+      cplx<R>* cw = reinterpret_cast<cplx<R>*>(P.cb) + (int64_t)pc.w * P.g.P * T * NP;
+      const int lo = pc.lo, hi = pc.hi, rb = pc.rb, s = pc.s;
+      const bool live = s < NB;
+      const bool fast = hi - lo + 1 <= kSsWaves;
+      const int idx = threadIdx.x, er = idx / NP, ec = idx % NP;  // this thread's element
+      const bool mine = idx < 16 * NP;
+      // the caller's right-hand side of the first sweep (does not depend on the wait)
+      double2 rhs = make_double2(0.0, 0.0);
+      if (live && pc.phase == 0 && !pc.second && mine) {
+        const int64_t r = (int64_t)s * T + 16 * rb + er;
+        if (ec < P.k && r < P.n) rhs = P.Bm[(int64_t)pc.w * P.bstride + (int64_t)ec * P.n + r];
       }
-    }
-    // A-role operand of inner index x: pointer, mask, row-major storage
-    auto operand = [&](int x, int& mask, bool& xt) -> const cplx<R>* {
-      if (phase == 0) {
-        mask = SM_NONE;
-        xt = ADJ != (bool)second;  // U tiles (row-major) in this sweep
-        return ADJ ? tile(x, s) : tile(s, x);
-      }
-      const int j = x;
-      if (!ADJ) {
-        mask = j == i ? (second ? SM_UPPER : SM_UNIT_LOWER) : SM_NONE;
-        xt = second && j != i;       // (U-hat^-1)_ij row-major, (L-hat^-1)_ij column-major
-        return j == i ? tile(s, s) : sbt(s, sb_slot(i, j));
-      }
-      mask = j == i ? (second ? SM_UNIT_LOWER : SM_UPPER) : SM_NONE;
-      xt = !second && j != i;        // ((U-hat^-1)_ji)^H or ((L-hat^-1)_ji)^H
-      return j == i ? tile(s, s) : sbt(s0 + j, sb_slot(j, i));
-    };
-    // this wave's chunks: tiles x = lo + wave, lo + wave + kSsWaves, ... (NCH
-    // chunks each); chunk 0's factor data does not depend on the wait and
-    // is loaded before it
-    constexpr int QC = ss_qc<R, T, NCB>(), NCH = (T / 4) / QC;
-    const int nch = lo + wave <= hi ? ((hi - lo - wave) / kSsWaves + 1) * NCH : 0;
-    auto load = [&](SChunk<R, T, NCB>& c, int idx, bool with_a, bool with_b) {
-      const int x = lo + wave + (idx / NCH) * kSsWaves, q0 = (idx % NCH) * QC;
-      if (with_a) {
-        int mask;
-        bool xt;
-        const cplx<R>* a = operand(x, mask, xt);
-        sc_load_a<R, T, ADJ, NCB>(c, a, mask, rb, xt, q0);
-      }
-      if (with_b)
-        sc_load_b<R, T, NP, NCB>(c, phase == 0 ? xw + (int64_t)x * T * NP
-                                               : cw + (int64_t)x * T * NP, q0);
-    };
-    SChunk<R, T, NCB> c0;
-    if (nch > 0) load(c0, 0, true, false);
-    if (s < NB && phase == 0 && !second) {  // the caller's right-hand side (row-fastest)
-      const double2* Bw = P.Bm + (int64_t)w * P.bstride;
-      for (int idx = threadIdx.x; idx < 16 * NP; idx += NT) {
-        const int rr = idx % 16, c = idx / 16;
-        const int64_t r = (int64_t)s * T + 16 * rb + rr;
-        double2 v = make_double2(0.0, 0.0);
-        if (c < P.k && r < P.n) v = Bw[(int64_t)c * P.n + r];
-        bin[rr * NP + c] = v;
-      }
-    }
-    // the step this piece waits for
-    if (phase == 1) {
-      ss_wait(counter(second, S, 0), npc, P.status);
-    } else if (!second) {
-      if (S > 0) ss_wait(counter(0, S - 1, 1), npc, P.status);
-    } else {
-      if (S == NS - 1) ss_wait(counter(0, NS - 1, 1), npc, P.status);
-      else ss_wait(counter(1, S + 1, 1), npc, P.status);
-    }
-    if (s < NB) {
-      SAcc<R, NCB> acc;
-      acc.zero();
-      if (phase == 0 && second) {  // the first sweep's y_s
-        const cplx<R>* ys = xw + (int64_t)s * T * NP;
-        for (int idx = threadIdx.x; idx < 16 * NP; idx += NT) {
-          const int rr = idx / NP, c = idx % NP;
-          cplx<R> v = ys[(16 * rb + rr) * NP + c];
-          bin[idx] = make_double2((double)v.re, (double)v.im);
+      // a long piece (more tiles than waves) walks its tiles in chunks of QC
+      // k-steps, two buffers, a chunk ahead; chunk 0's factor data is
+      // loaded before the wait
+      constexpr int QC = ss_qc<R, T, NCB>(), NCH = QA / QC;
+      const int nch = !fast && lo + wave <= hi ? ((hi - lo - wave) / kSsWaves + 1) * NCH : 0;
+      auto load = [&](SChunk<R, T, NCB>& c, int q, bool with_a, bool with_b) {
+        const int x = lo + wave + (q / NCH) * kSsWaves, q0 = (q % NCH) * QC;
+        if (with_a) {
+          int mask;
+          bool xt;
+          const cplx<R>* a = ss_operand<R, T, ADJ>(P, pc, x, mask, xt);
+          sc_load_a<R, T, ADJ, NCB>(c, a, mask, rb, xt, q0);
         }
-      }
-      //   phase A:  -sum_t T_st x_t       (the waves take the tiles in turn)
-      //   phase B:  sum_j (D-hat^-1)_ij c_j
-      if (nch > 0) load(c0, 0, false, true);
-      if constexpr (NCH == 1) {  // one buffer: a chunk is a whole tile
-        for (int idx = 0; idx < nch; idx++) {
-          if (idx > 0) load(c0, idx, true, true);
-          sc_mma<R, T, NCB, ADJ>(acc, c0);
+        if (with_b)
+          sc_load_b<R, T, NP, NCB>(c, pc.phase == 0 ? xw + (int64_t)x * T * NP
+                                                    : cw + (int64_t)x * T * NP, q0);
+      };
+      SChunk<R, T, NCB> c0;
+      if (nch > 0) load(c0, 0, true, false);
+      // the step this piece waits for (and, in the home team, the next ticket)
+      int* dep = nullptr;
+      if (pc.phase == 1) dep = counter(pc.second, pc.S, 0);
+      else if (!pc.second) dep = pc.S > 0 ? counter(0, pc.S - 1, 1) : nullptr;
+      else dep = pc.S == NS - 1 ? counter(0, NS - 1, 1) : counter(1, pc.S + 1, 1);
+      int64_t nxt = ss_wait(dep, npc, P.status, ahead ? tick : nullptr, &s_next);
+      SPiece pn = pc;
+      SPre<R, T> pren;
+      if (ahead) pn = ss_decode(nxt, team, P.teams, nw, npc, RPT, P.g);
+      // the next piece's operand: at once for a short piece (in flight
+      // during this one's products), after the products for a long one
+      // (whose chunk buffers would otherwise hold registers beside it)
+      const bool pf = ahead && nxt < total;
+      if (pf && (fast || !live)) ss_prefetch<R, T, ADJ>(pren, P, pn, wave);
+      if (live) {
+        if (pc.phase == 0 && pc.second && mine) {  // the first sweep's y_s
+          const cplx<R> v = xw[((int64_t)s * T + 16 * rb + er) * NP + ec];
+          rhs = make_double2((double)v.re, (double)v.im);
         }
-      } else {                         // two buffers, one chunk ahead
-        SChunk<R, T, NCB> c1;
-        for (int idx = 0; idx < nch; idx += 2) {
-          if (idx + 1 < nch) load(c1, idx + 1, true, true);
-          sc_mma<R, T, NCB, ADJ>(acc, c0);
-          if (idx + 1 < nch) {
-            if (idx + 2 < nch) load(c0, idx + 2, true, true);
-            sc_mma<R, T, NCB, ADJ>(acc, c1);
+        //   phase A:  -sum_t T_st x_t       (the waves take the tiles in turn)
+        //   phase B:  sum_j (D-hat^-1)_ij c_j
+        SAcc<R, NCB> acc;
+        acc.zero();
+        if (fast) {
+          const int x = lo + wave;
+          if (x <= hi) {
+            int mask;
+            bool xt;
+            const cplx<R>* X = ss_operand<R, T, ADJ>(P, pc, x, mask, xt);
+            const cplx<R>* V = (pc.phase == 0 ? xw : cw) + (int64_t)x * T * NP;
+            ss_short<R, T, NP, ADJ>(acc, pre, X, V, mask, rb, xt);
+          }
+        } else if (nch > 0) {
+          load(c0, 0, false, true);
+          SChunk<R, T, NCB> c1;
+          for (int q = 0; q < nch; q += 2) {
+            if (q + 1 < nch) load(c1, q + 1, true, true);
+            sc_mma<R, T, NCB, ADJ>(acc, c0);
+            if (q + 1 < nch) {
+              if (q + 2 < nch) load(c0, q + 2, true, true);
+              sc_mma<R, T, NCB, ADJ>(acc, c1);
+            }
           }
         }
-      }
-      // the waves' parts into LDS, summed in a fixed order
+        if (pf && !fast) ss_prefetch<R, T, ADJ>(pren, P, pn, wave);
+        // the waves' parts into LDS, summed in a fixed order
+        const int l = threadIdx.x & 63;
 #pragma unroll
-      for (int c = 0; c < NCB; c++)
+        for (int c = 0; c < NCB; c++)
 #pragma unroll
-        for (int e = 0; e < 4; e++)
-          red[(wave * 16 + Mf<R>::row(l, e)) * NP + 16 * c + (l & 15)] =
-              sc_finish<R, NCB>(acc, c, e, phase == 0);
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < 16 * NP; idx += NT) {
-        R sr = 0, sm = 0;
-        if (phase == 0) {
-          const double2 b = bin[idx];
-          sr = (R)b.x;
-          sm = (R)b.y;
-        }
-#pragma unroll
-        for (int v = 0; v < kSsWaves; v++) {
-          const cplx<R> p = red[v * 16 * NP + idx];
-          sr += p.re;
-          sm += p.im;
-        }
-        const int rr = idx / NP, c = idx % NP;
-        cplx<R>* dst = phase == 0 ? cw + (int64_t)i * T * NP : xw + (int64_t)s * T * NP;
-        st_coherent(dst + (16 * rb + rr) * NP + c, cplx<R>{sr, sm});
-        outb[idx] = cplx<R>{sr, sm};
-      }
-      if (phase == 1 && second) {  // the solution into the caller's block (row-fastest)
+          for (int e = 0; e < 4; e++)
+            red[(wave * 16 + Mf<R>::row(l, e)) * NP + 16 * c + (l & 15)] =
+                sc_finish<R, NCB>(acc, c, e, pc.phase == 0);
         __syncthreads();
-        double2* Xw = P.X + (int64_t)w * P.k * P.n;
-        for (int idx = threadIdx.x; idx < 16 * NP; idx += NT) {
-          const int rr = idx % 16, c = idx / 16;
-          const int64_t r = (int64_t)s * T + 16 * rb + rr;
-          if (c < P.k && r < P.n) {
-            const cplx<R> v = outb[rr * NP + c];
-            Xw[(int64_t)c * P.n + r] = make_double2((double)v.re, (double)v.im);
+        if (mine) {
+          R sr = (R)rhs.x, sm = (R)rhs.y;  // zero in phase B
+#pragma unroll
+          for (int v = 0; v < kSsWaves; v++) {
+            const cplx<R> p = red[v * 16 * NP + idx];
+            sr += p.re;
+            sm += p.im;
+          }
+          cplx<R>* dst = pc.phase == 0 ? cw + (int64_t)pc.i * T * NP : xw + (int64_t)s * T * NP;
+          st_coherent(dst + (16 * rb + er) * NP + ec, cplx<R>{sr, sm});
+          if (pc.phase == 1 && pc.second) {  // the solution into the caller's block
+            const int64_t r = (int64_t)s * T + 16 * rb + er;
+            if (ec < P.k && r < P.n)
+              P.X[((int64_t)pc.w * P.k + ec) * P.n + r] = make_double2((double)sr, (double)sm);
           }
         }
       }
+      ss_done(counter(pc.second, pc.S, pc.phase));
+      if (!ahead) {
+        nxt = wg_ticket(tick, &s_ticket);
+        pn = ss_decode(nxt, team, P.teams, nw, npc, RPT, P.g);
+        if (nxt < total) ss_prefetch<R, T, ADJ>(pren, P, pn, wave);
+      }
+      cur = nxt;
+      pc = pn;
+      pre = pren;
     }
-    ss_done(counter(second, S, phase));
-   }
   }
 }
 
