@@ -353,21 +353,25 @@ __device__ __forceinline__ void ss_mma(SAcc<R, NCB>& acc, const cplx<R>* a, cons
 }
 
 // The products of a short piece's wave: its tile X (A role, chunk 0 already
-// in pre) against the solved block V.
-template <typename R, int T, int NP, bool CA>
+// in pre) against the solved block V.  `later` issues the loads the products
+// do not need; it runs once the first operands' loads are issued, since
+// loads complete in order and the MFMAs would otherwise wait on them too.
+template <typename R, int T, int NP, bool CA, typename F>
 __device__ __forceinline__ void ss_short(SAcc<R, NP / 16>& acc, SPre<R, T>& pre,
                                          const cplx<R>* X, const cplx<R>* V, int mask, int rb,
-                                         bool xt) {
+                                         bool xt, F&& later) {
   constexpr int NCB = NP / 16, PQ = ss_pq<R, T>(), NCK = (T / 4) / PQ;
   cplx<R> ba[NCB][PQ];
   ss_load_b<R, NP, NCB, PQ>(ba, V, 0);
   if constexpr (NCK == 1) {
+    later();
     ss_mask_a<R, CA, PQ>(pre.a, mask, rb, 0);
     ss_mma<R, NCB, PQ, CA>(acc, pre.a, ba);
   } else {
     cplx<R> aa[PQ], ab[PQ], bb[NCB][PQ];
     ss_load_a<R, T, CA, PQ>(ab, X, rb, xt, PQ);
     ss_load_b<R, NP, NCB, PQ>(bb, V, PQ);
+    later();
     ss_mask_a<R, CA, PQ>(pre.a, mask, rb, 0);
     ss_mma<R, NCB, PQ, CA>(acc, pre.a, ba);
 #pragma unroll
@@ -391,15 +395,22 @@ __device__ __forceinline__ void ss_short(SAcc<R, NP / 16>& acc, SPre<R, T>& pre,
   }
 }
 
+// Loads the first chunk of a short piece's tile for this wave.  The loads
+// are issued whatever the piece (from the first stored tile when the wave
+// has nothing to load), so that the code around them has no branch: with
+// loads on one side of a branch only, the compiler's wait counts after it
+// are taken for the worst path, and the products would wait for this
+// prefetch as well.
 template <typename R, int T, bool ADJ>
 __device__ __forceinline__ void ss_prefetch(SPre<R, T>& pre, const SSolveParams& P, const SPiece& p,
-                                            int wave) {
+                                            int wave, bool want) {
   const int x = p.lo + wave;
-  if (p.hi - p.lo + 1 > kSsWaves || x > p.hi) return;
+  const bool ok = want && p.hi - p.lo + 1 <= kSsWaves && x <= p.hi;
   int mask;
-  bool xt;
-  const cplx<R>* X = ss_operand<R, T, ADJ>(P, p, x, mask, xt);
-  ss_load_a<R, T, ADJ, ss_pq<R, T>()>(pre.a, X, p.rb, xt, 0);
+  bool xt = false;
+  const cplx<R>* X = reinterpret_cast<const cplx<R>*>(P.tiles);
+  if (ok) X = ss_operand<R, T, ADJ>(P, p, x, mask, xt);
+  ss_load_a<R, T, ADJ, ss_pq<R, T>()>(pre.a, X, ok ? p.rb : 0, xt, 0);
 }
 
 template <typename R, int T, int NP, bool ADJ>
@@ -433,7 +444,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
     int64_t cur = wg_ticket(tick, &s_ticket);
     SPiece pc = ss_decode(cur, team, P.teams, nw, npc, RPT, P.g);
     SPre<R, T> pre;
-    if (cur < total) ss_prefetch<R, T, ADJ>(pre, P, pc, wave);
+    ss_prefetch<R, T, ADJ>(pre, P, pc, wave, cur < total);
     while (cur < total) {
       int* cnt_w = P.cnt + (int64_t)pc.w * 2 * NS * 2;
       auto counter = [&](int sw, int sup, int ph) { return cnt_w + ((int64_t)sw * NS + sup) * 2 + ph; };
@@ -478,16 +489,19 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
       SPiece pn = pc;
       SPre<R, T> pren;
       if (ahead) pn = ss_decode(nxt, team, P.teams, nw, npc, RPT, P.g);
-      // the next piece's operand: at once for a short piece (in flight
-      // during this one's products), after the products for a long one
-      // (whose chunk buffers would otherwise hold registers beside it)
+      // loads this piece's products do not wait for: the next piece's
+      // operand (in flight during this piece's products; for a long piece
+      // after them, whose chunk buffers would otherwise hold registers beside
+      // it) and the second sweep's right-hand side y_s
       const bool pf = ahead && nxt < total;
-      if (pf && (fast || !live)) ss_prefetch<R, T, ADJ>(pren, P, pn, wave);
+      const bool want_ys = live && pc.phase == 0 && pc.second && mine;
+      cplx<R> ys;  // (both loads unconditional: see ss_prefetch)
+      auto later = [&]() {
+        ys = xw[want_ys ? ((int64_t)s * T + 16 * rb + er) * NP + ec : 0];
+        ss_prefetch<R, T, ADJ>(pren, P, pn, wave, pf);
+      };
+      if (!live) later();
       if (live) {
-        if (pc.phase == 0 && pc.second && mine) {  // the first sweep's y_s
-          const cplx<R> v = xw[((int64_t)s * T + 16 * rb + er) * NP + ec];
-          rhs = make_double2((double)v.re, (double)v.im);
-        }
         //   phase A:  -sum_t T_st x_t       (the waves take the tiles in turn)
         //   phase B:  sum_j (D-hat^-1)_ij c_j
         SAcc<R, NCB> acc;
@@ -499,7 +513,9 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
             bool xt;
             const cplx<R>* X = ss_operand<R, T, ADJ>(P, pc, x, mask, xt);
             const cplx<R>* V = (pc.phase == 0 ? xw : cw) + (int64_t)x * T * NP;
-            ss_short<R, T, NP, ADJ>(acc, pre, X, V, mask, rb, xt);
+            ss_short<R, T, NP, ADJ>(acc, pre, X, V, mask, rb, xt, later);
+          } else {
+            later();
           }
         } else if (nch > 0) {
           load(c0, 0, false, true);
@@ -513,7 +529,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
             }
           }
         }
-        if (pf && !fast) ss_prefetch<R, T, ADJ>(pren, P, pn, wave);
+        if (!fast) later();
         // the waves' parts into LDS, summed in a fixed order
         const int l = threadIdx.x & 63;
 #pragma unroll
@@ -523,6 +539,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
             red[(wave * 16 + Mf<R>::row(l, e)) * NP + 16 * c + (l & 15)] =
                 sc_finish<R, NCB>(acc, c, e, pc.phase == 0);
         __syncthreads();
+        if (want_ys) rhs = make_double2((double)ys.re, (double)ys.im);
         if (mine) {
           R sr = (R)rhs.x, sm = (R)rhs.y;  // zero in phase B
 #pragma unroll
@@ -544,7 +561,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
       if (!ahead) {
         nxt = wg_ticket(tick, &s_ticket);
         pn = ss_decode(nxt, team, P.teams, nw, npc, RPT, P.g);
-        if (nxt < total) ss_prefetch<R, T, ADJ>(pren, P, pn, wave);
+        ss_prefetch<R, T, ADJ>(pren, P, pn, wave, nxt < total);
       }
       cur = nxt;
       pc = pn;
