@@ -128,8 +128,10 @@ typedef struct {
                             or when the error it leaves, estimated as e_j
                             times the contraction per correction (the ratio
                             of two successive corrections, this solve's or the
-                            largest kept per shift and direction since the
-                            factorisation), is at most tol / 2; for the
+                            largest kept per shift since the factorisation,
+                            shared by forward and adjoint solves, whose
+                            iteration matrices are similar), is at most
+                            tol / 2; for the
                             projection (step 4) and recovery (step 6) solves
                             (default 1e-10)                                     */
   double  refine_tol_sketch; /* mixed only: the same test for the sketch and

@@ -235,7 +235,7 @@ hipError_t launch_gmres_finish(int64_t n, int n_omega, int k, const GmresWs& g, 
 // direction (the ratio of successive corrections; rr_small.hip), is below
 // tol / 2.
 constexpr int kRhoStride = 64;  // doubles per shift in SmallWs::rho
-constexpr int kRhoSlot = 62;    // [62] forward, [63] adjoint: measured contraction
+constexpr int kRhoSlot = 62;    // [62]: measured contraction (both directions)
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D,
                                 double tol, int it, int adjoint, SmallWs& ws, uint32_t* status,
                                 uint32_t* fail_count, hipStream_t s,

@@ -580,18 +580,21 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
 
 // After X += D, per column j: e_j = ||D_j|| / ||X_j||, the size of the
 // correction just applied.  Refinement shrinks the error by a contraction
-// rho = ||I - M32^-1 M|| (per shift and direction) per correction, so the
-// error left is about rho e_j.  rho is never assumed: it is measured as the
-// ratio of two successive corrections, e_j / e_j,prev, and kept per shift
-// and direction as the largest ratio seen since the factorisation (slot
-// kRhoSlot + adjoint of the shift's row; zero = not measured yet).  A column
-// has converged when e_j <= tol, or when the error it leaves, estimated with
-// rho (this solve's own ratio from the second correction on, else the one
-// kept from earlier solves), is at most tol / 2.  So the first solve in each
-// direction after a factorisation takes a second correction unless the
-// first already meets tol, and later ones stop after one when the measured
-// contraction allows it.  Unconverged columns are counted into *fail_count
-// (reset by the caller per correction).
+// rho per correction, the rate of the iteration matrix I - M32^-1 M
+// (forward) or I - M32^-H M^H (adjoint), so the error left is about rho e_j.
+// rho is never assumed: it is measured as the ratio of two successive
+// corrections, e_j / e_j,prev, and kept per shift as the largest ratio seen
+// since the factorisation (slot kRhoSlot of the shift's row; zero = not
+// measured yet).  Both directions share it: the adjoint iteration matrix is
+// the conjugate transpose of I - M M32^-1 = M (I - M32^-1 M) M^-1, similar
+// to the forward one, so the two have the same eigenvalues and the ratios
+// converge to the same rate.  A column has converged when e_j <= tol, or
+// when the error it leaves, estimated with rho (this solve's own ratio from
+// the second correction on, else the kept one), is at most tol / 2.  So the
+// first solve after a factorisation takes a second correction unless the
+// first already meets tol, and later ones, in either direction, stop after
+// one when the measured contraction allows it.  Unconverged columns are
+// counted into *fail_count (reset by the caller per correction).
 __global__ void k_refine_check(int k, int nchunk, const double* px, const double* pd, double tol,
                                int it, int adjoint, double* rho, uint32_t* fail_count,
                                uint32_t* status, const uint32_t* skip) {
@@ -620,7 +623,8 @@ __global__ void k_refine_check(int k, int nchunk, const double* px, const double
     }
   }
   __syncthreads();
-  double* kept = rw + kRhoSlot + (adjoint ? 1 : 0);
+  double* kept = rw + kRhoSlot;
+  (void)adjoint;
   const double rho_kept = *kept;
   if (j < k) {
     rw[j] = e;
