@@ -78,6 +78,8 @@ SOLVE_CASES = [  # (nx, ny, tile, k): ragged n and b, several tiles per half-ban
     (9, 48, 64, 20),
     (16, 96, 32, 12),   # B = 6 tiles per half-band: early/final task split
     (12, 100, 64, 32),  # B = 4 at the 64 tile, ragged n, k = 32
+    (8, 160, 32, 20),   # B = 10 at the 32 tile: superblock steps with more tiles than waves
+    (6, 288, 64, 20),   # B = 9 at the 64 tile: the same at the benchmark's tile
 ]
 
 
