@@ -56,79 +56,96 @@ hipError_t launch_burgers_coeffs(int nx, int ny, const double* U, double hx, dou
   return hipGetLastError();
 }
 
-// Y = Bm - M X  (or Y = M X when Bm == NULL), M = i omega I - L, for one
-// column j (blockIdx.y) of shift w (blockIdx.z); one thread per node (both
-// components).  Adjoint: M^H = conj(i omega) I - L^T, whose stencil reads the
-// transposed coefficients from the neighbouring nodes.
+// Y = Bm - M X  (or Y = M X when Bm == NULL), M = i omega I - L, for all k
+// columns of shift w (blockIdx.y); one thread per node (both components),
+// which reads the node's stencil once and applies it to every column.
+// Adjoint: M^H = conj(i omega) I - L^T, whose stencil reads the transposed
+// coefficients from the neighbouring nodes.
 __global__ void k_apply(int nx, int ny, const double* __restrict__ coef,
                         const double* __restrict__ omega, int k, int adjoint,
                         const double2* __restrict__ X, const double2* __restrict__ Bm,
                         int64_t bstride, double2* __restrict__ Y, const uint32_t* skip) {
   if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  int nn = nx * ny;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn = nx * ny;
   if (p >= nn) return;
-  int j = blockIdx.y, w = blockIdx.z;
-  int64_t n = 2 * (int64_t)nn;
-  int64_t off = ((int64_t)w * k + j) * n;
-  const double2* x = X + off;
-  int i = p / ny, jj = p % ny;
-  bool hE = i < nx - 1, hW = i > 0, hN = jj < ny - 1, hS = jj > 0;
-  int pE = p + ny, pW = p - ny, pN = p + 1, pS = p - 1;
+  const int w = blockIdx.y;
+  const int64_t n = 2 * (int64_t)nn;
+  const int i = p / ny, jj = p % ny;
+  const bool hE = i < nx - 1, hW = i > 0, hN = jj < ny - 1, hS = jj > 0;
+  const int pE = p + ny, pW = p - ny, pN = p + 1, pS = p - 1;
   const double* c = coef + 12 * (int64_t)p;
-  double2 xu = x[2 * p], xv = x[2 * p + 1];
-  double lu_r, lu_i, lv_r, lv_i;  // (L x) or (L^T x) at rows 2p, 2p+1
+  // (L x) or (L^T x) at rows 2p, 2p+1:
+  //   u: au * x_u(p) + auv * x_v(p) + sum over neighbours q of eu[q] * x_u(q)
+  //   v: av * x_v(p) + avu * x_u(p) + sum over neighbours q of ev[q] * x_v(q)
+  // neighbours in the order E, W, N, S (forward) or W, E, S, N (adjoint)
+  double au, auv, av, avu, eu[4], ev[4];
+  int nb[4];
+  bool has[4];
   if (!adjoint) {
-    lu_r = c[0] * xu.x + c[5] * xv.x;
-    lu_i = c[0] * xu.y + c[5] * xv.y;
-    lv_r = c[6] * xv.x + c[11] * xu.x;
-    lv_i = c[6] * xv.y + c[11] * xu.y;
-    if (hE) { double2 a = x[2 * pE], b = x[2 * pE + 1];
-      lu_r += c[1] * a.x; lu_i += c[1] * a.y; lv_r += c[7] * b.x; lv_i += c[7] * b.y; }
-    if (hW) { double2 a = x[2 * pW], b = x[2 * pW + 1];
-      lu_r += c[2] * a.x; lu_i += c[2] * a.y; lv_r += c[8] * b.x; lv_i += c[8] * b.y; }
-    if (hN) { double2 a = x[2 * pN], b = x[2 * pN + 1];
-      lu_r += c[3] * a.x; lu_i += c[3] * a.y; lv_r += c[9] * b.x; lv_i += c[9] * b.y; }
-    if (hS) { double2 a = x[2 * pS], b = x[2 * pS + 1];
-      lu_r += c[4] * a.x; lu_i += c[4] * a.y; lv_r += c[10] * b.x; lv_i += c[10] * b.y; }
+    au = c[0]; auv = c[5]; av = c[6]; avu = c[11];
+    nb[0] = pE; has[0] = hE; eu[0] = c[1]; ev[0] = c[7];
+    nb[1] = pW; has[1] = hW; eu[1] = c[2]; ev[1] = c[8];
+    nb[2] = pN; has[2] = hN; eu[2] = c[3]; ev[2] = c[9];
+    nb[3] = pS; has[3] = hS; eu[3] = c[4]; ev[3] = c[10];
   } else {
     // (L^T x)_{2p} = uC_p xu_p + vCpl_p xv_p + uE_W xu_W + uW_E xu_E + uN_S xu_S + uS_N xu_N
-    lu_r = c[0] * xu.x + c[11] * xv.x;
-    lu_i = c[0] * xu.y + c[11] * xv.y;
-    lv_r = c[6] * xv.x + c[5] * xu.x;
-    lv_i = c[6] * xv.y + c[5] * xu.y;
-    if (hW) { const double* cw = coef + 12 * (int64_t)pW; double2 a = x[2 * pW], b = x[2 * pW + 1];
-      lu_r += cw[1] * a.x; lu_i += cw[1] * a.y; lv_r += cw[7] * b.x; lv_i += cw[7] * b.y; }
-    if (hE) { const double* ce = coef + 12 * (int64_t)pE; double2 a = x[2 * pE], b = x[2 * pE + 1];
-      lu_r += ce[2] * a.x; lu_i += ce[2] * a.y; lv_r += ce[8] * b.x; lv_i += ce[8] * b.y; }
-    if (hS) { const double* cs = coef + 12 * (int64_t)pS; double2 a = x[2 * pS], b = x[2 * pS + 1];
-      lu_r += cs[3] * a.x; lu_i += cs[3] * a.y; lv_r += cs[9] * b.x; lv_i += cs[9] * b.y; }
-    if (hN) { const double* cn = coef + 12 * (int64_t)pN; double2 a = x[2 * pN], b = x[2 * pN + 1];
-      lu_r += cn[4] * a.x; lu_i += cn[4] * a.y; lv_r += cn[10] * b.x; lv_i += cn[10] * b.y; }
+    au = c[0]; auv = c[11]; av = c[6]; avu = c[5];
+    const int qs[4] = {pW, pE, pS, pN};
+    const bool hs[4] = {hW, hE, hS, hN};
+    const int cu[4] = {1, 2, 3, 4};
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+      nb[d] = qs[d];
+      has[d] = hs[d];
+      const double* cq = coef + 12 * (int64_t)(hs[d] ? qs[d] : p);
+      eu[d] = cq[cu[d]];
+      ev[d] = cq[cu[d] + 6];
+    }
   }
   // shift: M = (i omega) I - L; i omega = -om_i + i om_r; M^H shift = conj of it
-  double sr = -omega[2 * w + 1], si = adjoint ? -omega[2 * w] : omega[2 * w];
-  double2 mu, mv;
-  mu.x = sr * xu.x - si * xu.y - lu_r;
-  mu.y = sr * xu.y + si * xu.x - lu_i;
-  mv.x = sr * xv.x - si * xv.y - lv_r;
-  mv.y = sr * xv.y + si * xv.x - lv_i;
-  double2* y = Y + off;
-  if (Bm) {
-    const double2* b = Bm + (int64_t)w * bstride + (int64_t)j * n;
-    double2 bu = b[2 * p], bv = b[2 * p + 1];
-    mu.x = bu.x - mu.x; mu.y = bu.y - mu.y;
-    mv.x = bv.x - mv.x; mv.y = bv.y - mv.y;
+  const double sr = -omega[2 * w + 1], si = adjoint ? -omega[2 * w] : omega[2 * w];
+  for (int j = 0; j < k; j++) {
+    const int64_t off = ((int64_t)w * k + j) * n;
+    const double2* x = X + off;
+    const double2 xu = x[2 * p], xv = x[2 * p + 1];
+    double lu_r = au * xu.x + auv * xv.x;
+    double lu_i = au * xu.y + auv * xv.y;
+    double lv_r = av * xv.x + avu * xu.x;
+    double lv_i = av * xv.y + avu * xu.y;
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+      if (!has[d]) continue;
+      const double2 a = x[2 * nb[d]], b = x[2 * nb[d] + 1];
+      lu_r += eu[d] * a.x;
+      lu_i += eu[d] * a.y;
+      lv_r += ev[d] * b.x;
+      lv_i += ev[d] * b.y;
+    }
+    double2 mu, mv;
+    mu.x = sr * xu.x - si * xu.y - lu_r;
+    mu.y = sr * xu.y + si * xu.x - lu_i;
+    mv.x = sr * xv.x - si * xv.y - lv_r;
+    mv.y = sr * xv.y + si * xv.x - lv_i;
+    if (Bm) {
+      const double2* bb = Bm + (int64_t)w * bstride + (int64_t)j * n;
+      const double2 bu = bb[2 * p], bv = bb[2 * p + 1];
+      mu.x = bu.x - mu.x;
+      mu.y = bu.y - mu.y;
+      mv.x = bv.x - mv.x;
+      mv.y = bv.y - mv.y;
+    }
+    double2* y = Y + off;
+    y[2 * p] = mu;
+    y[2 * p + 1] = mv;
   }
-  y[2 * p] = mu;
-  y[2 * p + 1] = mv;
 }
 
 hipError_t launch_apply(const OpDesc& op, const double* omega, int n_omega, int k, int adjoint,
                         const double* X, const double* Bm, int64_t bstride, double* Y,
                         hipStream_t s, const uint32_t* skip) {
   int nn = op.nx * op.ny;
-  dim3 grid((nn + 255) / 256, k, n_omega);
+  dim3 grid((nn + 255) / 256, n_omega);
   hipLaunchKernelGGL(k_apply, grid, dim3(256), 0, s, op.nx, op.ny, op.coef, omega, k, adjoint,
                      (const double2*)X, (const double2*)Bm, bstride, (double2*)Y, skip);
   return hipGetLastError();
