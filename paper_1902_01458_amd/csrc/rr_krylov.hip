@@ -266,6 +266,164 @@ __global__ __launch_bounds__(kKThreads) void k_pc_ilu0_apply(int nx, int ny, int
   }
 }
 
+// The same sweeps with one thread per grid column j (ny <= kIluColMax):
+// thread j walks its nodes (i, j), i = 0 .. nx-1 (backward: nx-1 .. 0), at
+// anti-diagonal steps d = i + j.  Its own previous node, (i-1, j) (backward
+// (i+1, j)), stays in registers; only the other neighbour, (i, j-1)
+// (backward (i, j+1)), comes through LDS from the neighbouring thread's
+// previous step.  A node's operands (x or the forward result, the two
+// off-diagonal blocks, D^-1) do not depend on the sweep, so each thread loads
+// its next node's while it computes the current one, into the other of two
+// register sets (chosen by the parity of d, the same for every thread).  The
+// loads are issued by every thread at every step (of a valid node, kept or
+// not) and hold raw coefficients (signs applied at use): a load that is
+// conditional, or whose value is transformed at once, makes the compiler
+// wait for it, or for the loads around it, before the step's arithmetic.
+// The arithmetic is the same, in the same order, as k_pc_ilu0_apply's.
+constexpr int kIluColMax = 512;
+
+struct IluOp {
+  double2 v0, v1;      // x_p (forward) or w_p (backward)
+  double a0, a1;       // minus the block to the (i, j -/+ 1) neighbour
+  double b0, b1;       // minus the block to the (i -/+ 1, j) neighbour
+  C2 D;
+};
+
+__global__ __launch_bounds__(kIluColMax) void k_pc_ilu0_apply_col(
+    int nx, int ny, int k, int adjoint, const double* __restrict__ coef,
+    const double2* __restrict__ Dinv, const double2* X, double2* Y, const uint32_t* active,
+    const uint32_t* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  extern __shared__ __align__(16) char kc_smem[];
+  double2* ring = reinterpret_cast<double2*>(kc_smem);  // [2][ny][2]
+  const int c = blockIdx.x, w = blockIdx.y, nn = nx * ny;
+  const int64_t q = (int64_t)w * k + c;
+  if (active && !active[q]) return;
+  const int64_t off = q * 2 * nn;
+  const double2* x = X + off;
+  double2* y = Y + off;
+  const double2* Dw = Dinv + (int64_t)w * nn * 4;
+  const bool herm = adjoint != 0;
+  const int j = threadIdx.x;
+  const bool col = j < ny;
+  const int jc = col ? j : ny - 1;  // the column whose nodes this thread loads
+  const int nd = nx + ny - 1;
+  // raw loads of node (clamp(i), jc); the blocks are minus the loaded values
+  auto fwd_load = [&](int i, IluOp& o) {
+    i = min(max(i, 0), nx - 1);
+    const int p = jc + ny * i;
+    const double* cp = coef + 12 * (int64_t)p;
+    o.v0 = x[2 * p];
+    o.v1 = x[2 * p + 1];
+    const double* cw = coef + 12 * (int64_t)(jc > 0 ? p - 1 : p);
+    const double* ca = herm ? cw + 3 : cp + 4;
+    o.a0 = ca[0];
+    o.a1 = ca[6];
+    const double* cn = coef + 12 * (int64_t)(i > 0 ? p - ny : p);
+    const double* cb = herm ? cn + 1 : cp + 2;
+    o.b0 = cb[0];
+    o.b1 = cb[6];
+    o.D = load_c2(Dw + (int64_t)p * 4);
+  };
+  auto bwd_load = [&](int i, IluOp& o) {
+    i = min(max(i, 0), nx - 1);
+    const int p = jc + ny * i;
+    const double* cp = coef + 12 * (int64_t)p;
+    o.v0 = y[2 * p];
+    o.v1 = y[2 * p + 1];
+    const double* ce = coef + 12 * (int64_t)(jc < ny - 1 ? p + 1 : p);
+    const double* ca = herm ? ce + 4 : cp + 3;
+    o.a0 = ca[0];
+    o.a1 = ca[6];
+    const double* cs = coef + 12 * (int64_t)(i < nx - 1 ? p + ny : p);
+    const double* cb = herm ? cs + 2 : cp + 1;
+    o.b0 = cb[0];
+    o.b1 = cb[6];
+    o.D = load_c2(Dw + (int64_t)p * 4);
+  };
+  IluOp opA, opB;  // the register sets of even and odd steps
+  double2 own0 = make_double2(0, 0), own1 = make_double2(0, 0);
+  // forward: w_p = D_p^-1 (x_p - M_p,p-1 w_p-1 - M_p,p-ny w_p-ny)
+  if (j & 1) fwd_load(0, opB);
+  else fwd_load(0, opA);
+  auto fwd_step = [&](int d, IluOp& use, IluOp& fill) {
+    const int i = d - j;
+    double2* cur = ring + (d & 1) * 2 * ny;
+    const double2* prev = ring + ((d + 1) & 1) * 2 * ny;
+    fwd_load(i + 1, fill);
+    if (col && i >= 0 && i < nx) {
+      double2 r0 = use.v0, r1 = use.v1;
+      if (j > 0) {
+        r0 = csub(r0, cscale(-use.a0, prev[2 * (j - 1)]));
+        r1 = csub(r1, cscale(-use.a1, prev[2 * (j - 1) + 1]));
+      }
+      if (i > 0) {
+        r0 = csub(r0, cscale(-use.b0, own0));
+        r1 = csub(r1, cscale(-use.b1, own1));
+      }
+      double2 w0, w1;
+      mv2(use.D, herm, r0, r1, w0, w1);
+      cur[2 * j] = w0;
+      cur[2 * j + 1] = w1;
+      const int p = j + ny * i;
+      y[2 * p] = w0;
+      y[2 * p + 1] = w1;
+      own0 = w0;
+      own1 = w1;
+    }
+    __syncthreads();
+  };
+  int d = 0;
+  for (; d + 1 < nd; d += 2) {
+    fwd_step(d, opA, opB);
+    fwd_step(d + 1, opB, opA);
+  }
+  if (d < nd) fwd_step(d, opA, opB);
+  // backward: y_p = w_p - D_p^-1 (M_p,p+1 y_p+1 + M_p,p+ny y_p+ny); the
+  // forward results of this thread's own column are its own stores
+  if ((nx - 1 + j) & 1) bwd_load(nx - 1, opB);
+  else bwd_load(nx - 1, opA);
+  auto bwd_step = [&](int d, IluOp& use, IluOp& fill) {
+    const int i = d - j;
+    double2* cur = ring + (d & 1) * 2 * ny;
+    const double2* nxt = ring + ((d + 1) & 1) * 2 * ny;
+    bwd_load(i - 1, fill);
+    if (col && i >= 0 && i < nx) {
+      double2 t0 = make_double2(0, 0), t1 = make_double2(0, 0);
+      if (j < ny - 1) {
+        t0 = cadd(t0, cscale(-use.a0, nxt[2 * (j + 1)]));
+        t1 = cadd(t1, cscale(-use.a1, nxt[2 * (j + 1) + 1]));
+      }
+      if (i < nx - 1) {
+        t0 = cadd(t0, cscale(-use.b0, own0));
+        t1 = cadd(t1, cscale(-use.b1, own1));
+      }
+      double2 u0, u1;
+      mv2(use.D, herm, t0, t1, u0, u1);
+      const double2 y0 = csub(use.v0, u0), y1 = csub(use.v1, u1);
+      cur[2 * j] = y0;
+      cur[2 * j + 1] = y1;
+      const int p = j + ny * i;
+      y[2 * p] = y0;
+      y[2 * p + 1] = y1;
+      own0 = y0;
+      own1 = y1;
+    }
+    __syncthreads();
+  };
+  d = nd - 1;
+  for (; d - 1 >= 0; d -= 2) {
+    if (d & 1) {
+      bwd_step(d, opB, opA);
+      bwd_step(d - 1, opA, opB);
+    } else {
+      bwd_step(d, opA, opB);
+      bwd_step(d - 1, opB, opA);
+    }
+  }
+  if (d == 0) bwd_step(0, opA, opB);
+}
+
 // partial[(q * nchunk + chunk) * 2 + e] = sum over the chunk of conj(A_e) B_e
 // for the npair (1 or 2) pairs, per system q = w * k + c.
 __global__ __launch_bounds__(kKThreads) void k_kdot_partial(int64_t n, int k, int npair,
@@ -460,6 +618,9 @@ hipError_t prepare_krylov(int ny) {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_pc_ilu0_apply,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)ilu0_apply_lds(ny));
+  if (e == hipSuccess && ny <= kIluColMax)
+    e = hipFuncSetAttribute((const void*)k_pc_ilu0_apply_col,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ilu0_apply_lds(ny));
   return e;
 }
 
@@ -479,7 +640,11 @@ hipError_t launch_pc_apply(const OpDesc& op, int precond, int n_omega, int k, in
                            const double* Dinv, const double* X, double* Y,
                            const uint32_t* active, const uint32_t* skip, hipStream_t s) {
   const int nn = op.nx * op.ny;
-  if (precond == RR_PRECOND_ILU0)
+  if (precond == RR_PRECOND_ILU0 && op.ny <= kIluColMax)
+    hipLaunchKernelGGL(k_pc_ilu0_apply_col, dim3(k, n_omega), dim3((op.ny + 63) / 64 * 64),
+                       ilu0_apply_lds(op.ny), s, op.nx, op.ny, k, adjoint, op.coef,
+                       (const double2*)Dinv, (const double2*)X, (double2*)Y, active, skip);
+  else if (precond == RR_PRECOND_ILU0)
     hipLaunchKernelGGL(k_pc_ilu0_apply, dim3(k, n_omega), dim3(kKThreads), ilu0_apply_lds(op.ny),
                        s, op.nx, op.ny, k, adjoint, op.coef, (const double2*)Dinv,
                        (const double2*)X, (double2*)Y, active, skip);
