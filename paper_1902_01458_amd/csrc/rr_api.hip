@@ -521,7 +521,7 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
     f->flag_count = pl.nflags;
   } else {        // the preconditioner and the Krylov vectors
     const size_t cols = (size_t)n_omega * k_max, cplx = 2 * sizeof(double);
-    ALLOC(f->pc_dinv, (size_t)n_omega * nn * 4 * cplx);
+    ALLOC(f->pc_dinv, pc_bytes(f->precond, p->nx, p->ny, n_omega));
     const int nvec = solver == RR_SOLVER_BICGSTAB ? 7 : 1;
     for (int v = 0; v < nvec; v++) ALLOC(f->kv[v], pl.vec);
     ALLOC(f->kpart, cols * krylov_nchunk(n64) * 2 * cplx);

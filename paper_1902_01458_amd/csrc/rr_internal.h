@@ -260,6 +260,7 @@ hipError_t launch_cols_copy(int64_t n, int n_omega, int k, int64_t wstride, int 
 // LU-free Krylov solves (rr_krylov.hip)
 int krylov_nchunk(int64_t n);
 size_t ilu0_lds(int ny);
+size_t pc_bytes(int precond, int nx, int ny, int n_omega);
 hipError_t prepare_krylov(int ny);
 // Dinv[w][p] (4 complex): the inverted node blocks of the preconditioner
 hipError_t launch_pc_setup(const OpDesc& op, int precond, const double* omega, int n_omega,
