@@ -126,12 +126,17 @@ typedef struct {
   double  refine_tol;    /* mixed only: a column has converged when its last
                             correction d_j has e_j = ||d_j|| / ||x_j|| <= tol,
                             or when the error it leaves, estimated as e_j
-                            times the contraction per correction (the ratio
-                            of two successive corrections, this solve's or the
-                            largest kept per shift since the factorisation,
-                            shared by forward and adjoint solves, whose
-                            iteration matrices are similar), is at most
-                            tol / 2; for the
+                            times the contraction per correction, is at most
+                            tol / 2.  The contraction is measured, never
+                            assumed: on the first refined solve after a
+                            factorisation by probe systems M x = M z with
+                            known z solved in the solve's spare columns (a
+                            forward solve with 4 or more spare, e.g. k = 20
+                            of 32) or else by the ratio of two successive
+                            corrections; the largest value since the
+                            factorisation is kept per shift and shared by
+                            forward and adjoint solves, whose iteration
+                            matrices are similar.  For the
                             projection (step 4) and recovery (step 6) solves
                             (default 1e-10)                                     */
   double  refine_tol_sketch; /* mixed only: the same test for the sketch and

@@ -81,7 +81,7 @@ void free_all(rr_factors* f) {
                 f->gm.V, f->gm.t, f->gm.H, f->gm.h, f->gm.beta, f->gm.y, f->gm.partial,
                 f->pc_dinv, f->kv[0], f->kv[1], f->kv[2], f->kv[3], f->kv[4], f->kv[5],
                 f->kv[6], f->kpart, f->kscal, f->kbnorm, f->kactive, f->small.big1,
-                f->small.big2, f->wide_tmp};
+                f->small.big2, f->wide_tmp, f->probe_b, f->probe_x, f->probe_r, f->probe_z};
   for (void* p : ps) {
     if (!p) continue;
     if (f->dealloc) f->dealloc(p, f->alloc_ctx);
@@ -102,6 +102,16 @@ constexpr int kMaxRefine = 16;
 // Sketch widths above this take the wide k x k kernels (rr_bigk.hip) and
 // band solves in groups of this many columns (FP64 only).
 constexpr int kNarrowK = 32;
+
+// Refinement probes: the columns a solve of k columns has spare (the solve
+// runs solve_np(k) of them), at most kMaxProbes; fewer than kMinProbes are
+// not used.
+constexpr int kMinProbes = 4, kMaxProbes = 12;
+constexpr uint64_t kProbeSeed = 0x70726f6265ull;  // the probes' Philox key
+int probe_cols(int k, int np_max) {
+  const int p = std::min(solve_np(k), np_max) - k;
+  return p >= kMinProbes ? std::min(p, kMaxProbes) : 0;
+}
 
 // The k x k steps for narrow (k <= 32: LDS-resident) or wide sketches.
 hipError_t cholqr(rr_factors* f, int n_omega, int k, double* Y, hipStream_t s) {
@@ -271,34 +281,65 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
     return RR_OK;
   }
   const bool mixed = f->prec == RR_MIXED;
+  const bool refine = mixed && tol < 1.0;  // a tolerance of 1 or more asks for no correction
+  // The first refined solve after a factorisation measures the contraction.
+  // Where a forward solve has spare columns (it runs solve_np(k)), p probe
+  // systems M x = M z with known z ride along in them: their exact errors
+  // before and after the first correction give it, so no second correction
+  // is needed for the measurement.
+  const int p = refine && f->rho_fresh && !adjoint && f->gm.m == 0 && f->probe_z
+                    ? std::min(probe_cols(k, f->probe_np), f->probe_p)
+                    : 0;
+  if (refine) f->rho_fresh = false;
+  const int kk = k + p;
+  const int64_t n = f->n, pblk = (int64_t)kk * n;
+  const double* B1 = Bm;
+  int64_t bs1 = bstride;
+  double* X1 = X;
+  double* res = f->work3;
+  if (p > 0) {  // [Bm | M z] into the probe block
+    RR_HIP(launch_cols_place(n, f->n_omega, k, Bm, bstride, 0, f->probe_b, pblk, 0, s));
+    RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, p, adjoint, f->probe_z, nullptr, 0,
+                        f->probe_r, s));
+    RR_HIP(launch_cols_place(n, f->n_omega, p, f->probe_r, (int64_t)p * n, 0, f->probe_b, pblk,
+                             k, s));
+    B1 = f->probe_b;
+    bs1 = pblk;
+    X1 = f->probe_x;
+    res = f->probe_r;
+  }
   if (f->tev[2]) RR_HIP(hipEventRecord(f->tev[2], s));
-  RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, mixed, f->tiles, adjoint, Bm, bstride, X,
+  RR_HIP(launch_solve(f->geom, f->n, f->n_omega, kk, mixed, f->tiles, adjoint, B1, bs1, X1,
                       f->xs, f->cbuf, f->flags, ticket_word(f), st_word(f), f->solve_grid, s));
   if (f->tev[3]) RR_HIP(hipEventRecord(f->tev[3], s));
-  if (!mixed || tol >= 1.0) return RR_OK;  // a tolerance of 1 or more asks for no correction
-  double* res = f->work3;
+  if (!refine) return RR_OK;
+  if (p > 0)
+    RR_HIP(launch_probe_errors(f->n, f->n_omega, kk, k, p, X1, f->probe_z, f->small, st_word(f),
+                               s));
   RR_HIP(launch_fill_u32(conv_word(f), 0u, 1, s));
   for (int it = 0; it < f->refine_iters; it++) {
     // res = Bm - M X in FP64 from the stencil, then res <- M32^-1 res (or the
     // GMRES-IR correction), X += res
-    RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, k, adjoint, X, Bm, bstride, res, s,
+    RR_HIP(launch_apply(opdesc(f), f->omega, f->n_omega, kk, adjoint, X1, B1, bs1, res, s,
                         conv_word(f)));
     if (f->gm.m > 0) {
       RR_HIP(gmres_correction(f, k, adjoint, res, s));
     } else {
-      RR_HIP(launch_solve(f->geom, f->n, f->n_omega, k, true, f->tiles, adjoint, res,
-                          (int64_t)k * f->n, res, f->xs, f->cbuf, f->flags, ticket_word(f),
-                          st_word(f), f->solve_grid, s, conv_word(f)));
+      RR_HIP(launch_solve(f->geom, f->n, f->n_omega, kk, true, f->tiles, adjoint, res, pblk, res,
+                          f->xs, f->cbuf, f->flags, ticket_word(f), st_word(f), f->solve_grid, s,
+                          conv_word(f)));
     }
     RR_HIP(launch_fill_u32(fail_word(f), 0u, 1, s));
-    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X, res, tol, it, adjoint, f->small,
-                                st_word(f), fail_word(f), s, conv_word(f)));
+    RR_HIP(launch_refine_update(f->n, f->n_omega, k, X1, res, tol, it, adjoint, f->small,
+                                st_word(f), fail_word(f), s, conv_word(f), kk, p, f->probe_z));
     hipLaunchKernelGGL(k_refine_step, dim3(1), dim3(64), 0, s, (const uint32_t*)fail_word(f),
                        f->ctrl + 4 + it, conv_word(f));
   }
   hipLaunchKernelGGL(k_latch_unless, dim3(1), dim3(64), 0, s, (const uint32_t*)conv_word(f),
                      st_word(f), (uint32_t)ST_NOT_CONVERGED);
   RR_HIP(hipGetLastError());
+  if (p > 0)  // the caller's columns back
+    RR_HIP(launch_cols_place(n, f->n_omega, k, X1, pblk, 0, X, (int64_t)k * n, 0, s));
   return RR_OK;
 }
 
@@ -306,12 +347,12 @@ rr_status solve_any(rr_factors* f, int k, int adjoint, const double* Bm, int64_t
 struct Plan {
   BandGeom geom;
   size_t coef, phi, U, omega, tiles, xs, cbuf, flags, ctrl, theta, vec, work3, partial, kk2, rho,
-      shifted, grad, big = 0, wide = 0;
-  int nchunk, grad_nchunk;
+      shifted, grad, big = 0, wide = 0, probe_blk = 0, probe_z = 0;
+  int nchunk, grad_nchunk, probe_np = 0, probe_p = 0;
   size_t nflags;
   size_t total() const {
     return coef + phi + U + omega + tiles + xs + cbuf + flags + ctrl + theta + 2 * vec + work3 +
-           partial + 5 * kk2 + rho + shifted + grad + 2 * big + wide;
+           partial + 5 * kk2 + rho + shifted + grad + 2 * big + wide + 3 * probe_blk + probe_z;
   }
 };
 
@@ -325,7 +366,7 @@ int superblock_tiles(int want, int T, int B) {
 }
 
 Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T, bool has_phi,
-               bool has_U, int sb) {
+               bool has_U, int sb, bool probes) {
   Plan pl{};
   const int64_t n = 2 * (int64_t)nx * ny;
   const size_t nn = (size_t)nx * ny;
@@ -352,7 +393,8 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   pl.nchunk = (int)((n + 2047) / 2048);
   const size_t kk = (size_t)std::max(k_max * k_max, 64);
   const size_t kkn = (size_t)std::max(kn * kn, 64);
-  pl.partial = (size_t)n_omega * std::max<size_t>(pl.nchunk * kkn,
+  // (at least 96 complex per chunk: the refinement's three partial rows of 64)
+  pl.partial = (size_t)n_omega * std::max<size_t>(pl.nchunk * std::max<size_t>(kkn, 96),
                                                   k_max > kNarrowK ? gramb_chunks(n) * kk : 0) *
                2 * sizeof(double);
   if (k_max > kNarrowK) {  // the wide k x k steps' scratch and one wide block
@@ -361,6 +403,12 @@ Plan make_plan(int nx, int ny, int n_omega, int k_max, rr_precision prec, int T,
   }
   pl.kk2 = (size_t)n_omega * kk * 2 * sizeof(double);
   pl.rho = prec == RR_MIXED ? (size_t)n_omega * kRhoStride * sizeof(double) : 0;
+  if (prec == RR_MIXED && probes && probe_cols(kn, solve_np(kn)) > 0) {
+    pl.probe_np = solve_np(kn);
+    pl.probe_p = probe_cols(kn, pl.probe_np);
+    pl.probe_blk = (size_t)n_omega * pl.probe_np * n * 2 * sizeof(double);
+    pl.probe_z = (size_t)n_omega * pl.probe_p * n * 2 * sizeof(double);
+  }
   pl.shifted = (size_t)n_omega * sizeof(uint32_t);
   pl.grad_nchunk = (int)(((size_t)(nx + 2) * (ny + 2) + 255) / 256);  // k_grad's blocks
   pl.grad = (size_t)n_omega * pl.grad_nchunk * 2 * sizeof(double);
@@ -500,8 +548,9 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   }
   hipStream_t s = (hipStream_t)stream;
   const size_t nn = (size_t)p->nx * p->ny;
+  const bool gmres_ir = prec == RR_MIXED && tune && tune->refine_method == RR_REFINE_GMRES;
   const Plan pl = make_plan(p->nx, p->ny, n_omega, k_max, prec, T, p->phi != nullptr,
-                            p->U != nullptr, tune ? tune->superblock : 0);
+                            p->U != nullptr, tune ? tune->superblock : 0, !krylov && !gmres_ir);
   f->tile_bytes = pl.tiles;
   rr_status st = RR_OK;
 #define ALLOC(ptr, bytes)                      \
@@ -541,6 +590,14 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   ALLOC(f->small.W, pl.kk2);
   ALLOC(f->small.Ut, pl.kk2);
   if (prec == RR_MIXED) ALLOC(f->small.rho, pl.rho);
+  if (pl.probe_blk) {
+    ALLOC(f->probe_b, pl.probe_blk);
+    ALLOC(f->probe_x, pl.probe_blk);
+    ALLOC(f->probe_r, pl.probe_blk);
+    ALLOC(f->probe_z, pl.probe_z);
+    f->probe_np = pl.probe_np;
+    f->probe_p = pl.probe_p;
+  }
   ALLOC(f->small.shifted, pl.shifted);
   if (k_max > kNarrowK) {
     ALLOC(f->small.big1, pl.big);
@@ -606,6 +663,23 @@ rr_status rr_factor(const rr_problem* p, const double* omega_re, const double* o
   }
   st = rr_refactor(f, stream);
   if (st != RR_OK) goto fail_free;
+  if (f->probe_z) {
+    // The probes' known solutions: FP32 solves of complex Gaussian forcing,
+    // so that they have the make-up of the responses the refinement meets
+    // (the contraction measured on white-noise probes came out up to 2x
+    // smaller than on the solutions themselves; on such responses within
+    // about 10 %).  Any vectors would do: the probes solve M x = M z for z.
+    hipError_t e = launch_sketch(opdesc(f), nullptr, f->probe_p, kProbeSeed, RR_TM_GAUSSIAN, 0,
+                                 f->probe_r, s);
+    if (e == hipSuccess)
+      e = launch_solve(f->geom, f->n, n_omega, f->probe_p, true, f->tiles, 0, f->probe_r, 0,
+                       f->probe_z, f->xs, f->cbuf, f->flags, ticket_word(f), st_word(f),
+                       f->solve_grid, s);
+    if (e != hipSuccess) {
+      st = fail(RR_ERR_HIP, hipGetErrorString(e));
+      goto fail_free;
+    }
+  }
   // the omega upload reads a host vector owned by the handle: nothing to wait for
   *out = f;
   return RR_OK;
@@ -636,6 +710,7 @@ rr_status rr_refactor(rr_factors* f, void* stream) {
   // a new factor: the refinement's measured contractions no longer hold
   if (e == hipSuccess && f->small.rho)
     e = launch_refine_reset(f->n_omega, f->small.rho, (hipStream_t)stream);
+  f->rho_fresh = f->small.rho != nullptr;
   if (e != hipSuccess) {
     f->sticky_hip_error = true;
     return fail(RR_ERR_HIP, std::string("factor launch: ") + hipGetErrorString(e));
@@ -824,6 +899,10 @@ rr_status rr_check(rr_factors* f, void* stream) {
   }
   uint32_t ctrl[4 + kMaxRefine];
   e = hipMemcpy(ctrl, f->ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) {  // the correction counts restart at every check
+    const uint32_t zeros[kMaxRefine] = {};
+    e = hipMemcpy(f->ctrl + 4, zeros, sizeof(zeros), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     f->sticky_hip_error = true;
     return fail(RR_ERR_HIP, hipGetErrorString(e));
@@ -917,7 +996,7 @@ size_t rr_factor_bytes(int32_t nx, int32_t ny, int32_t n_omega, int32_t k_max, r
   if (k_max > (prec == RR_FP64 ? kMaxWideK : kNarrowK)) return 0;
   const int T = tile ? tile : 64;
   if (T != 32 && T != 64) return 0;
-  return make_plan(nx, ny, n_omega, k_max, prec, T, true, true, 0).total();
+  return make_plan(nx, ny, n_omega, k_max, prec, T, true, true, 0, true).total();
 }
 
 // ---------------------------------------------------------------------------

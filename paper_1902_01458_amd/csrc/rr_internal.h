@@ -236,10 +236,24 @@ hipError_t launch_gmres_finish(int64_t n, int n_omega, int k, const GmresWs& g, 
 // tol / 2.
 constexpr int kRhoStride = 64;  // doubles per shift in SmallWs::rho
 constexpr int kRhoSlot = 62;    // [62]: measured contraction (both directions)
+constexpr int kProbeSlot = 32;  // [32, 32 + p): the probe columns' errors before correcting
+// X += D over the first kk columns (default k), the converged test on the
+// first k; with probes (p > 0: columns k .. k+p-1 solve M x = M z for the
+// known z of Z, p blocks of n per shift) the first correction (it = 0) also
+// measures the contraction on them.
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D,
                                 double tol, int it, int adjoint, SmallWs& ws, uint32_t* status,
                                 uint32_t* fail_count, hipStream_t s,
-                                const uint32_t* skip = nullptr);
+                                const uint32_t* skip = nullptr, int kk = 0, int p = 0,
+                                const double* Z = nullptr);
+// The probe columns' errors ||X_{k0+q} - Z_q|| (q < p) after the first solve,
+// kept in the contraction rows for the first correction.
+hipError_t launch_probe_errors(int n, int n_omega, int kk, int k0, int p, const double* X,
+                               const double* Z, SmallWs& ws, uint32_t* status, hipStream_t s);
+// ncols columns from src (shift stride sws complex, 0 = shared; first column
+// sc0) to dst (shift stride dws, first column dc0); columns are n long
+hipError_t launch_cols_place(int64_t n, int n_omega, int ncols, const double* src, int64_t sws,
+                             int sc0, double* dst, int64_t dws, int dc0, hipStream_t s);
 // Zero the measured contractions of every shift (after a refactorisation).
 hipError_t launch_refine_reset(int n_omega, double* rho, hipStream_t s);
 // Wide sketches, 32 < k <= kMaxWideK (rr_bigk.hip), FP64 only
@@ -345,6 +359,15 @@ struct rr_factors {
   double* work1 = nullptr;
   double* work2 = nullptr;
   double* work3 = nullptr;
+  // refinement probes (mixed, plain refinement): probe_np columns per shift
+  // in the blocks b, x, r (right-hand sides, solutions, residuals) and
+  // probe_p known solutions z per shift
+  double* probe_b = nullptr;
+  double* probe_x = nullptr;
+  double* probe_r = nullptr;
+  double* probe_z = nullptr;
+  int probe_np = 0, probe_p = 0;
+  bool rho_fresh = false;             // no solve has measured the contraction since the factor
   rr::SmallWs small{};
   double* grad_partial = nullptr;
   int grad_nchunk = 0;

@@ -490,28 +490,44 @@ hipError_t launch_small_svd(int n, int n_omega, int k, const double* Z, const do
 }
 
 // partial[w][chunk][j] = sum over the chunk of |X_j|^2 (and of |D_j|^2 into
-// partial2 when D != NULL, after X += D).
+// partial2 when D != NULL, after X += D).  Block (chunk, w, z) takes columns
+// 4z .. 4z+3; each thread owns rows r0 + t + 256 i of the chunk and issues
+// all of a column's loads before it adds them up (in i order), so a column
+// costs one memory round trip.
+constexpr int kColGroup = 4;
 __global__ __launch_bounds__(256) void k_colnorm_partial(int64_t n, int k, double2* X,
                                                          const double2* __restrict__ D,
                                                          int nchunk, double* partial,
                                                          double* partial2, const uint32_t* skip) {
   if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  constexpr int RPT = kChunkRows / 256;
   __shared__ double red[2][256];
   const int w = blockIdx.y, chunk = blockIdx.x;
-  int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
-  for (int j = 0; j < k; j++) {
+  const int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
+  const int j1 = min(k, kColGroup * ((int)blockIdx.z + 1));
+  for (int j = kColGroup * blockIdx.z; j < j1; j++) {
     double2* x = X + ((int64_t)w * k + j) * n;
     const double2* d = D ? D + ((int64_t)w * k + j) * n : nullptr;
+    double2 xv[RPT], dv[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; i++) {
+      const int64_t r = r0 + threadIdx.x + 256 * i;
+      xv[i] = r < r1 ? x[r] : make_double2(0, 0);
+      dv[i] = d && r < r1 ? d[r] : make_double2(0, 0);
+    }
     double sx = 0, sd = 0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-      double2 v = x[r];
-      if (d) {
-        double2 dv = d[r];
-        sd += dv.x * dv.x + dv.y * dv.y;
-        v.x += dv.x; v.y += dv.y;
-        x[r] = v;
+#pragma unroll
+    for (int i = 0; i < RPT; i++) {
+      const int64_t r = r0 + threadIdx.x + 256 * i;
+      if (r < r1) {
+        double2 v = xv[i];
+        if (d) {
+          sd += dv[i].x * dv[i].x + dv[i].y * dv[i].y;
+          v.x += dv[i].x; v.y += dv[i].y;
+          x[r] = v;
+        }
+        sx += v.x * v.x + v.y * v.y;
       }
-      sx += v.x * v.x + v.y * v.y;
     }
     red[0][threadIdx.x] = sx;
     red[1][threadIdx.x] = sd;
@@ -530,6 +546,9 @@ __global__ __launch_bounds__(256) void k_colnorm_partial(int64_t n, int k, doubl
     __syncthreads();
   }
 }
+static dim3 colnorm_grid(int nc, int n_omega, int k) {
+  return dim3(nc, n_omega, (k + kColGroup - 1) / kColGroup);
+}
 
 __global__ void k_colnorm_final(int k, int nchunk, const double* partial, double* sigma,
                                 uint32_t* status) {
@@ -544,21 +563,34 @@ __global__ void k_colnorm_final(int k, int nchunk, const double* partial, double
 }
 
 // U_j = W_j / sigma_j (divide; 0 where sigma_j = 0) or W_j * sigma_j.
-__global__ void k_scale_cols(int64_t n, int k, const double2* W, const double* sigma, double2* U,
-                             int divide) {
-  int64_t r = blockIdx.x * (int64_t)256 + threadIdx.x;
-  int j = blockIdx.y, w = blockIdx.z;
-  if (r >= n) return;
-  double s = sigma[(int64_t)w * k + j];
-  double c = divide ? (s > 0 ? 1.0 / s : 0.0) : s;
-  int64_t off = ((int64_t)w * k + j) * n + r;
-  double2 v = W[off];
-  U[off] = make_double2(v.x * c, v.y * c);
+// Each thread takes kScaleRows rows, 256 apart.
+constexpr int kScaleRows = 8;
+__global__ __launch_bounds__(256) void k_scale_cols(int64_t n, int k, const double2* W,
+                                                    const double* sigma, double2* U, int divide) {
+  const int j = blockIdx.y, w = blockIdx.z;
+  const double s = sigma[(int64_t)w * k + j];
+  const double c = divide ? (s > 0 ? 1.0 / s : 0.0) : s;
+  const int64_t base = ((int64_t)w * k + j) * n;
+  const int64_t r0 = blockIdx.x * (int64_t)(256 * kScaleRows) + threadIdx.x;
+  double2 v[kScaleRows];
+#pragma unroll
+  for (int i = 0; i < kScaleRows; i++) {
+    const int64_t r = r0 + 256 * i;
+    v[i] = r < n ? W[base + r] : make_double2(0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < kScaleRows; i++) {
+    const int64_t r = r0 + 256 * i;
+    if (r < n) U[base + r] = make_double2(v[i].x * c, v[i].y * c);
+  }
+}
+static dim3 scale_grid(int n, int k, int n_omega) {
+  return dim3((unsigned)((n + 256 * kScaleRows - 1) / (256 * kScaleRows)), k, n_omega);
 }
 
 hipError_t launch_scale_cols(int n, int n_omega, int k, const double* W, const double* scale,
                              double* U, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, k, n_omega), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_scale_cols, scale_grid(n, k, n_omega), dim3(256), 0, s,
                      (int64_t)n, k, (const double2*)W, scale, (double2*)U, 0);
   return hipGetLastError();
 }
@@ -568,12 +600,13 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
   int nc = nchunks(n);
   if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
   double* part = ws.partial;
-  hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
+  hipLaunchKernelGGL(k_colnorm_partial, colnorm_grid(nc, n_omega, k), dim3(256), 0, s,
+                     (int64_t)n, k,
                      (double2*)W, (const double2*)nullptr, nc, part, (double*)nullptr,
                      (const uint32_t*)nullptr);
   hipLaunchKernelGGL(k_colnorm_final, dim3(n_omega), dim3(64), 0, s, k, nc, part, sigma, status);
   if (U)
-    hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, k, n_omega), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_scale_cols, scale_grid(n, k, n_omega), dim3(256), 0, s,
                        (int64_t)n, k, (const double2*)W, (const double*)sigma, (double2*)U, 1);
   return hipGetLastError();
 }
@@ -582,18 +615,21 @@ hipError_t launch_colnorm_scale(int n, int n_omega, int k, const double* W, doub
 // correction just applied.  Refinement shrinks the error by a contraction
 // rho per correction, the rate of the iteration matrix I - M32^-1 M
 // (forward) or I - M32^-H M^H (adjoint), so the error left is about rho e_j.
-// rho is never assumed: it is measured as the ratio of two successive
-// corrections, e_j / e_j,prev, and kept per shift as the largest ratio seen
-// since the factorisation (slot kRhoSlot of the shift's row; zero = not
-// measured yet).  Both directions share it: the adjoint iteration matrix is
+// rho is never assumed: it is measured, and kept per shift as the largest
+// value seen since the factorisation (slot kRhoSlot of the shift's row; zero
+// = not measured yet).  Two measurements: the ratio of two successive
+// corrections, e_j / e_j,prev; and, on the first solve after a
+// factorisation when the solve has spare columns, probe systems M x = M z
+// with z known, solved beside the caller's columns, whose errors before and
+// after the first correction are exact (k_probe_rho).  Both directions share it: the adjoint iteration matrix is
 // the conjugate transpose of I - M M32^-1 = M (I - M32^-1 M) M^-1, similar
 // to the forward one, so the two have the same eigenvalues and the ratios
 // converge to the same rate.  A column has converged when e_j <= tol, or
 // when the error it leaves, estimated with rho (this solve's own ratio from
 // the second correction on, else the kept one), is at most tol / 2.  So the
 // first solve after a factorisation takes a second correction unless the
-// first already meets tol, and later ones, in either direction, stop after
-// one when the measured contraction allows it.  Unconverged columns are
+// first already meets tol or its probes measured rho, and later ones, in
+// either direction, stop after one when the measured contraction allows it.  Unconverged columns are
 // counted into *fail_count (reset by the caller per correction).
 __global__ void k_refine_check(int k, int nchunk, const double* px, const double* pd, double tol,
                                int it, int adjoint, double* rho, uint32_t* fail_count,
@@ -636,6 +672,112 @@ __global__ void k_refine_check(int k, int nchunk, const double* px, const double
   if (threadIdx.x == 0 && it > 0) *kept = fmax(rho_kept, ratio_max);
 }
 
+// partial[w][chunk][q] = sum over the chunk of |X_{k0+q} - Z_q|^2, q < p: the
+// errors of the probe columns (X: kk columns per shift, Z: p per shift).
+__global__ __launch_bounds__(256) void k_probe_partial(int64_t n, int kk, int k0, int p,
+                                                       const double2* __restrict__ X,
+                                                       const double2* __restrict__ Z, int nchunk,
+                                                       double* partial, const uint32_t* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  constexpr int RPT = kChunkRows / 256;
+  __shared__ double red[256];
+  const int w = blockIdx.y, chunk = blockIdx.x;
+  const int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
+  for (int q = 0; q < p; q++) {
+    const double2* x = X + ((int64_t)w * kk + k0 + q) * n;
+    const double2* z = Z + ((int64_t)w * p + q) * n;
+    double2 xv[RPT], zv[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; i++) {
+      const int64_t r = r0 + threadIdx.x + 256 * i;
+      xv[i] = r < r1 ? x[r] : make_double2(0, 0);
+      zv[i] = r < r1 ? z[r] : make_double2(0, 0);
+    }
+    double se = 0;
+#pragma unroll
+    for (int i = 0; i < RPT; i++) {
+      const double dx = xv[i].x - zv[i].x, dy = xv[i].y - zv[i].y;
+      se += dx * dx + dy * dy;
+    }
+    red[threadIdx.x] = se;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[((int64_t)w * nchunk + chunk) * 64 + q] = red[0];
+    __syncthreads();
+  }
+}
+
+// The probes' errors e_q: after the first solve (stage 0) kept in the slots
+// kProbeSlot + q; after the first correction (stage 1) their ratio to those,
+// whose largest is the measured contraction rho (kept as in k_refine_check).
+__global__ void k_probe_rho(int p, int nchunk, const double* partial, int stage, double* rho,
+                            uint32_t* status, const uint32_t* skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  __shared__ double ratio_max;
+  const int w = blockIdx.x, q = threadIdx.x;
+  double* rw = rho + (int64_t)w * kRhoStride;
+  if (q == 0) ratio_max = 0.0;
+  __syncthreads();
+  if (q < p) {
+    double s = 0;
+    for (int c = 0; c < nchunk; c++) s += partial[((int64_t)w * nchunk + c) * 64 + q];
+    if (!isfinite(s)) latch(status, ST_NONFINITE);
+    const double e = sqrt(s);
+    if (stage == 0) {
+      rw[kProbeSlot + q] = e;
+    } else {
+      const double e0 = rw[kProbeSlot + q];
+      const double ratio = e0 > 0 ? e / e0 : (e > 0 ? INFINITY : 0.0);
+      atomicMax(reinterpret_cast<unsigned long long*>(&ratio_max),
+                (unsigned long long)__double_as_longlong(ratio));
+    }
+  }
+  __syncthreads();
+  if (q == 0 && stage == 1) rw[kRhoSlot] = fmax(rw[kRhoSlot], ratio_max);
+}
+
+hipError_t launch_probe_errors(int n, int n_omega, int kk, int k0, int p, const double* X,
+                               const double* Z, SmallWs& ws, uint32_t* status, hipStream_t s) {
+  const int nc = nchunks(n);
+  if (nc > ws.nchunk || p < 1 || p > 32 || k0 + p > kk || !ws.rho) return hipErrorInvalidValue;
+  double* pz = ws.partial + 2 * (size_t)n_omega * nc * 64;
+  hipLaunchKernelGGL(k_probe_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, kk, k0, p,
+                     (const double2*)X, (const double2*)Z, nc, pz, (const uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_probe_rho, dim3(n_omega), dim3(64), 0, s, p, nc, (const double*)pz, 0,
+                     ws.rho, status, (const uint32_t*)nullptr);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_cols_place(int64_t n, const double2* src, int64_t sws,
+                                                    int sc0, double2* dst, int64_t dws, int dc0) {
+  const int c = blockIdx.y, w = blockIdx.z;
+  const double2* a = src + w * sws + (int64_t)(sc0 + c) * n;
+  double2* b = dst + w * dws + (int64_t)(dc0 + c) * n;
+  const int64_t r0 = blockIdx.x * (int64_t)(256 * kScaleRows) + threadIdx.x;
+  double2 v[kScaleRows];
+#pragma unroll
+  for (int i = 0; i < kScaleRows; i++) {
+    const int64_t r = r0 + 256 * i;
+    v[i] = r < n ? a[r] : make_double2(0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < kScaleRows; i++) {
+    const int64_t r = r0 + 256 * i;
+    if (r < n) b[r] = v[i];
+  }
+}
+
+hipError_t launch_cols_place(int64_t n, int n_omega, int ncols, const double* src, int64_t sws,
+                             int sc0, double* dst, int64_t dws, int dc0, hipStream_t s) {
+  if (ncols < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_cols_place, scale_grid((int)n, ncols, n_omega), dim3(256), 0, s, n,
+                     (const double2*)src, sws, sc0, (double2*)dst, dws, dc0);
+  return hipGetLastError();
+}
+
 // Forget the measured contractions (a new factorisation).
 __global__ void k_refine_reset(int n_omega, double* rho) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
@@ -652,13 +794,23 @@ hipError_t launch_refine_reset(int n_omega, double* rho, hipStream_t s) {
 
 hipError_t launch_refine_update(int n, int n_omega, int k, double* X, const double* D, double tol,
                                 int it, int adjoint, SmallWs& ws, uint32_t* status,
-                                uint32_t* fail_count, hipStream_t s, const uint32_t* skip) {
+                                uint32_t* fail_count, hipStream_t s, const uint32_t* skip, int kk,
+                                int p, const double* Z) {
   int nc = nchunks(n);
-  if (nc > ws.nchunk || k > KM) return hipErrorInvalidValue;
+  if (kk < k) kk = k;
+  if (nc > ws.nchunk || kk > KM || (p > 0 && (!Z || k + p > kk))) return hipErrorInvalidValue;
   double* px = ws.partial;
   double* pd = ws.partial + (size_t)n_omega * nc * 64;
-  hipLaunchKernelGGL(k_colnorm_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, k,
+  hipLaunchKernelGGL(k_colnorm_partial, colnorm_grid(nc, n_omega, kk), dim3(256), 0, s,
+                     (int64_t)n, kk,
                      (double2*)X, (const double2*)D, nc, px, pd, skip);
+  if (p > 0 && it == 0) {  // the probes' errors after the first correction: rho
+    double* pz = ws.partial + 2 * (size_t)n_omega * nc * 64;
+    hipLaunchKernelGGL(k_probe_partial, dim3(nc, n_omega), dim3(256), 0, s, (int64_t)n, kk, k, p,
+                       (const double2*)X, (const double2*)Z, nc, pz, skip);
+    hipLaunchKernelGGL(k_probe_rho, dim3(n_omega), dim3(64), 0, s, p, nc, pz, 1, ws.rho, status,
+                       skip);
+  }
   hipLaunchKernelGGL(k_refine_check, dim3(n_omega), dim3(64), 0, s, k, nc, px, pd, tol, it,
                      adjoint, ws.rho, fail_count, status, skip);
   return hipGetLastError();

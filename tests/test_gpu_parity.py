@@ -262,3 +262,49 @@ def test_superblock_solve_matches_oracle(prec, nx, ny, tile, k, sb):
         ez = np.linalg.norm(Z[i] - refh) / np.linalg.norm(refh)
         assert ex <= tol and ez <= tol, (i, ex, ez)
     f.free()
+
+
+@pytest.mark.parametrize("k,probed", [(10, True), (20, True), (16, False)])
+def test_first_refined_solve_measures_contraction(k, probed):
+    """The first refined mixed solve after a factorisation measures the
+    refinement's contraction.  With spare solve columns (k = 10 of 16, 20 of
+    32) probe systems with known solutions ride along and measure it exactly
+    on the first correction, so one correction is enough; with none spare
+    (k = 16) a second correction measures it.  Every solve meets the
+    tolerance against LAPACK's banded solve, also after a refactorisation
+    (which measures again)."""
+    w = W.small("pr", 40, 24, nu=2e-2)
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    prob = rr().BurgersProblem.from_workload(w)
+    oms = [0.4, 2.5, 1.1]
+    f = rr().factor(prob, oms, "mixed", k_max=k, tile=32, refine_tol=1e-8)
+    rng = np.random.Generator(np.random.PCG64(31))
+    Bm = rng.standard_normal((3, k, w.n)) + 1j * rng.standard_normal((3, k, w.n))
+    Bt = torch.tensor(Bm, device="cuda")
+    refs = []
+    for i, om in enumerate(oms):
+        S = ShiftedSolver(op.shifted(L, om), "gb")
+        refs.append((S.solve(Bm[i].T).T, S.solve_adjoint(Bm[i].T).T))
+
+    def err(X, adj):
+        return max(np.linalg.norm(X[i] - refs[i][adj]) / np.linalg.norm(refs[i][adj])
+                   for i in range(3))
+
+    counts = []
+    for rep in range(2):
+        X = to_np(f.solve(Bt))
+        f.check()
+        counts.append(f.refine_count())
+        Z = to_np(f.adjoint_solve(Bt))
+        f.check()
+        counts.append(f.refine_count())
+        X2 = to_np(f.solve(Bt))
+        f.check()
+        counts.append(f.refine_count())
+        assert err(X, 0) <= 1e-8 and err(X2, 0) <= 1e-8 and err(Z, 1) <= 1e-8, \
+            (rep, err(X, 0), err(X2, 0), err(Z, 1))
+        f.refactor()
+    print(f"\nk = {k}: corrections per solve {counts}")
+    first = 1 if probed else 2
+    assert counts == [first, 1, 1] * 2, counts
+    f.free()
