@@ -417,14 +417,45 @@ __device__ __forceinline__ int tix(int i, int j, int T, bool rowmajor) {
 // or row-major (at i*lda + k); B: row-major (B[k][j] at k*ldb + j) or
 // column-major (at j*ldb + k); either may live in LDS or global memory.
 // Optional triangular masks apply to each stored tile's own indices.
-// Fragments of KQ k-steps are loaded before use.
-template <typename R, int T, int KQ, bool SUB>
+// Fragments of KQ k-steps are loaded before use.  G3: Gauss's three real
+// products per complex one (a_r b_r, a_i b_i, (a_r + a_i)(b_r + b_i)),
+// summed apart and combined at the end.
+template <typename R>
+struct Gauss3 {
+  typename Mf<R>::v4 p1[2], p2[2], p3[2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) { p1[b][e] = 0; p2[b][e] = 0; p3[b][e] = 0; }
+  }
+  __device__ __forceinline__ void mma(cplx<R> a, cplx<R> b, int c) {
+    p1[c] = Mf<R>::op(a.re, b.re, p1[c]);
+    p2[c] = Mf<R>::op(a.im, b.im, p2[c]);
+    p3[c] = Mf<R>::op(a.re + a.im, b.re + b.im, p3[c]);
+  }
+  template <bool SUB>
+  __device__ __forceinline__ void add_to(Acc2<R>& acc) const {
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const R re = p1[b][e] - p2[b][e], im = p3[b][e] - p1[b][e] - p2[b][e];
+        acc.re[b][e] += SUB ? -re : re;
+        acc.im[b][e] += SUB ? -im : im;
+      }
+  }
+};
+
+template <typename R, int T, int KQ, bool SUB, bool G3 = false>
 __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int lda, bool a_rowmajor,
                                           int amask, const cplx<R>* Bm, int ldb, bool b_colmajor,
                                           int bmask, int rb, int cp) {
   const int l = threadIdx.x & 63;
   const int i = 16 * rb + (l & 15);
   const int j0 = 32 * cp + (l & 15), j1 = j0 + 16;
+  Gauss3<R> g;
+  if constexpr (G3) g.zero();
 #pragma unroll 1
   for (int kq = 0; kq < T / 4; kq += KQ) {
     cplx<R> a[KQ], b0[KQ], b1[KQ];
@@ -446,10 +477,16 @@ __device__ __forceinline__ void tile_gemm(Acc2<R>& acc, const cplx<R>* A, int ld
     }
 #pragma unroll
     for (int q = 0; q < KQ; q++) {
-      cmfma<R, false, SUB>(acc.re[0], acc.im[0], a[q], b0[q]);
-      cmfma<R, false, SUB>(acc.re[1], acc.im[1], a[q], b1[q]);
+      if constexpr (G3) {
+        g.mma(a[q], b0[q], 0);
+        g.mma(a[q], b1[q], 1);
+      } else {
+        cmfma<R, false, SUB>(acc.re[0], acc.im[0], a[q], b0[q]);
+        cmfma<R, false, SUB>(acc.re[1], acc.im[1], a[q], b1[q]);
+      }
     }
   }
+  if constexpr (G3) g.template add_to<SUB>(acc);
 }
 
 // The diagonal tiles are not in the ticket order: the first n_omega
@@ -931,6 +968,58 @@ __device__ __forceinline__ cplx<R>* sb_ptr(const FactorParams& P, int w, int r, 
   return reinterpret_cast<cplx<R>*>(P.tiles) + idx * (T * T);
 }
 
+// acc += sum_{l = lo .. hi} A_il X_lj for the superblock inverse's block
+// substitution (k_sbinv): A_il the factor's tile (s0+i, s0+l) (L column-major,
+// or U row-major when upper), X_lj the inverse's tile already formed (stored
+// column-major, or row-major when upper).  The KQ-step chunks of all the
+// products form one sequence loaded a chunk ahead of the MFMAs.
+template <typename R, int T, int KQ, bool G3>
+__device__ __forceinline__ void sb_chain(Acc2<R>& acc, const FactorParams& P, int w, int s0, int i,
+                                         int lo, int hi, int j, bool upper, int rb, int cp) {
+  constexpr int NKC = T / 4 / KQ;  // chunks per product
+  static_assert(NKC % 2 == 0, "even chunk count");
+  const int N = (hi - lo + 1) * NKC;
+  if (N <= 0) return;
+  const int l = threadIdx.x & 63;
+  const int ii = 16 * rb + (l & 15), j0 = 32 * cp + (l & 15), j1 = j0 + 16;
+  Gauss3<R> g;
+  if constexpr (G3) g.zero();
+  auto load = [&](UpdChunk<R, T, KQ>& c, int idx) {
+    const int ll = lo + idx / NKC, kq = (idx % NKC) * KQ;
+    const cplx<R>* A = tile_ptr<R, T>(P, w, s0 + i, s0 + ll);
+    const cplx<R>* X = sb_ptr<R, T>(P, w, s0 + ll, sb_slot(ll, j));
+#pragma unroll
+    for (int q = 0; q < KQ; q++) {
+      const int k = 4 * (kq + q) + (l >> 4);
+      c.a[q] = upper ? A[ii * T + k] : A[k * T + ii];
+      c.b0[q] = upper ? X[k * T + j0] : X[j0 * T + k];
+      c.b1[q] = upper ? X[k * T + j1] : X[j1 * T + k];
+    }
+  };
+  auto mma = [&](const UpdChunk<R, T, KQ>& c) {
+#pragma unroll
+    for (int q = 0; q < KQ; q++) {
+      if constexpr (G3) {
+        g.mma(c.a[q], c.b0[q], 0);
+        g.mma(c.a[q], c.b1[q], 1);
+      } else {
+        cmfma<R, false, false>(acc.re[0], acc.im[0], c.a[q], c.b0[q]);
+        cmfma<R, false, false>(acc.re[1], acc.im[1], c.a[q], c.b1[q]);
+      }
+    }
+  };
+  UpdChunk<R, T, KQ> c0, c1;
+  load(c0, 0);
+#pragma unroll 1
+  for (int idx = 0; idx < N; idx += 2) {
+    load(c1, idx + 1);
+    mma(c0);
+    load(c0, min(idx + 2, N - 1));  // the last one reloads a chunk (unused)
+    mma(c1);
+  }
+  if constexpr (G3) g.template add_to<false>(acc);
+}
+
 // Off-diagonal tiles of the inverses of each superblock's diagonal block (the
 // block triangles L-hat and U-hat of P block rows), after the factorisation:
 //   L-hat^-1:  X_jj = L_jj^-1,  X_ij = -L_ii^-1 sum_{l=j}^{i-1} L_il X_lj   (i > j)
@@ -939,12 +1028,21 @@ __device__ __forceinline__ cplx<R>* sb_ptr(const FactorParams& P, int w, int r, 
 // (shift, superblock, triangle, column j) walks its column outward from the
 // diagonal; each tile it writes is read back by the later ones after a
 // barrier (same workgroup, same CU).  Products are T x T tile GEMMs on MFMA
-// with operands from memory; the sum is staged in LDS for the product with
-// the diagonal inverse.
+// with operands from memory (the ones with formed inverse tiles in one
+// pipelined sequence, sb_chain); the sum is staged in LDS for the product
+// with the diagonal inverse.  In FP32 the complex products are Gauss's three
+// real MFMAs: these inverses only serve the superblock solves, whose FP32
+// errors the FP64-residual refinement removes (the factor itself, which is
+// also the GMRES-IR preconditioner, keeps four).
 template <typename R, int T>
 __global__ __launch_bounds__(FGeom<T>::NT) void k_sbinv(FactorParams P) {
   typedef FGeom<T> G;
   constexpr int KQ = sizeof(R) == 8 ? 4 : 8;
+  constexpr bool G3 = sizeof(R) == 4;    // Gauss products in FP32
+  // FP32: sb_chain; FP64 loads each product's chunks in turn (a second
+  // chunk buffer would cost the FP64 kernel its second workgroup per CU)
+  constexpr bool PIPE = sizeof(R) == 4;
+  constexpr int KS = PIPE ? KQ / 2 : KQ;
   extern __shared__ __align__(16) char smem_raw[];
   cplx<R>* sacc = reinterpret_cast<cplx<R>*>(smem_raw);  // T x LDT, column-major
   cplx<R>* stage = sacc + T * G::LDT;
@@ -965,18 +1063,25 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_sbinv(FactorParams P) {
     const cplx<R>* Djj = tile_ptr<R, T>(P, w, s0 + j, s0 + j);
     for (int i = j + 1; i < PS && s0 + i < NB; i++) {
       acc.zero();
-      for (int l = j; l < i; l++) {
-        if (i - l > B) continue;  // outside the band: L_il = 0
-        const cplx<R>* X = l == j ? Djj : sb_ptr<R, T>(P, w, s0 + l, sb_slot(l, j));
-        tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + l), T, false, MK_NONE,
-                                   X, T, true, l == j ? MK_UNIT_LOWER : MK_NONE, rb, cp);
+      if constexpr (PIPE) {
+        if (i - j <= B)  // L_ij X_jj, X_jj = L_jj^-1 (outside the band L_il = 0)
+          tile_gemm<R, T, KQ, false, G3>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + j), T, false,
+                                         MK_NONE, Djj, T, true, MK_UNIT_LOWER, rb, cp);
+        sb_chain<R, T, KS, G3>(acc, P, w, s0, i, max(j + 1, i - B), i - 1, j, false, rb, cp);
+      } else {
+        for (int l = j; l < i; l++) {
+          if (i - l > B) continue;  // outside the band: L_il = 0
+          const cplx<R>* X = l == j ? Djj : sb_ptr<R, T>(P, w, s0 + l, sb_slot(l, j));
+          tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + l), T, false, MK_NONE,
+                                     X, T, true, l == j ? MK_UNIT_LOWER : MK_NONE, rb, cp);
+        }
       }
       __syncthreads();
       acc_to_lds<R, T>(acc, sacc, false, rb, cp);
       __syncthreads();
       acc.zero();
-      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false,
-                                MK_UNIT_LOWER, sacc, G::LDT, true, MK_NONE, rb, cp);
+      tile_gemm<R, T, KQ, true, G3>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false,
+                                    MK_UNIT_LOWER, sacc, G::LDT, true, MK_NONE, rb, cp);
       stage_store<R, T>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), false, rb, cp);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
@@ -987,18 +1092,25 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_sbinv(FactorParams P) {
     const cplx<R>* Djj = tile_ptr<R, T>(P, w, s0 + j, s0 + j);
     for (int i = j - 1; i >= 0; i--) {
       acc.zero();
-      for (int l = i + 1; l <= j; l++) {
-        if (l - i > B) continue;  // outside the band: U_il = 0
-        const cplx<R>* X = l == j ? Djj : sb_ptr<R, T>(P, w, s0 + l, sb_slot(l, j));
-        tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + l), T, true, MK_NONE,
-                                   X, T, l == j, l == j ? MK_UPPER : MK_NONE, rb, cp);
+      if constexpr (PIPE) {
+        sb_chain<R, T, KS, G3>(acc, P, w, s0, i, i + 1, min(j - 1, i + B), j, true, rb, cp);
+        if (j - i <= B)  // U_ij X_jj, X_jj = U_jj^-1 (outside the band U_il = 0)
+          tile_gemm<R, T, KQ, false, G3>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + j), T, true,
+                                         MK_NONE, Djj, T, true, MK_UPPER, rb, cp);
+      } else {
+        for (int l = i + 1; l <= j; l++) {
+          if (l - i > B) continue;  // outside the band: U_il = 0
+          const cplx<R>* X = l == j ? Djj : sb_ptr<R, T>(P, w, s0 + l, sb_slot(l, j));
+          tile_gemm<R, T, KQ, false>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + l), T, true, MK_NONE,
+                                     X, T, l == j, l == j ? MK_UPPER : MK_NONE, rb, cp);
+        }
       }
       __syncthreads();
       acc_to_lds<R, T>(acc, sacc, false, rb, cp);
       __syncthreads();
       acc.zero();
-      tile_gemm<R, T, KQ, true>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false, MK_UPPER,
-                                sacc, G::LDT, true, MK_NONE, rb, cp);
+      tile_gemm<R, T, KQ, true, G3>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false, MK_UPPER,
+                                    sacc, G::LDT, true, MK_NONE, rb, cp);
       stage_store<R, T>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), true, rb, cp);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();

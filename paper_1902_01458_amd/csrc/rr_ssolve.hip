@@ -223,6 +223,12 @@ constexpr size_t ssolve_lds() {  // the waves' partial sums of a piece
   return sizeof(cplx<R>) * (size_t)16 * NP * kSsWaves;
 }
 
+// Every piece is short (at most kSsWaves tiles of inner dimension): phase A
+// spans at most the half-band's B tiles, phase B at most the superblock's P.
+__host__ __device__ inline bool ss_all_short(const BandGeom& g) {
+  return g.B <= kSsWaves && g.P <= kSsWaves;
+}
+
 // One piece: 16 rows (row block rb of tile row i of superblock S) of one
 // phase of one sweep of shift w, and the tiles lo .. hi of its inner
 // dimension (band tiles outside the superblock in phase A, the superblock's
@@ -413,7 +419,10 @@ __device__ __forceinline__ void ss_prefetch(SPre<R, T>& pre, const SSolveParams&
   ss_load_a<R, T, ADJ, ss_pq<R, T>()>(pre.a, X, ok ? p.rb : 0, xt, 0);
 }
 
-template <typename R, int T, int NP, bool ADJ>
+// SHORT: every piece is short (the band and the superblock span at most
+// kSsWaves tiles), so the long-piece path is compiled out; its chunk buffers
+// would otherwise set the register count (in FP64 with spills).
+template <typename R, int T, int NP, bool ADJ, bool SHORT>
 __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
   if (P.skip && __hip_atomic_load(P.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   constexpr int NCB = NP / 16;
@@ -452,7 +461,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
       cplx<R>* cw = reinterpret_cast<cplx<R>*>(P.cb) + (int64_t)pc.w * P.g.P * T * NP;
       const int lo = pc.lo, hi = pc.hi, rb = pc.rb, s = pc.s;
       const bool live = s < NB;
-      const bool fast = hi - lo + 1 <= kSsWaves;
+      const bool fast = SHORT || hi - lo + 1 <= kSsWaves;
       const int idx = threadIdx.x, er = idx / NP, ec = idx % NP;  // this thread's element
       const bool mine = idx < 16 * NP;
       // the caller's right-hand side of the first sweep (does not depend on the wait)
@@ -572,8 +581,12 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
 
 template <typename R, int T, int NP, bool ADJ>
 static hipError_t ss_launch(const SSolveParams& P, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ>), dim3(grid), dim3(64 * kSsWaves),
-                     (ssolve_lds<R, T, NP>()), s, P);
+  if (ss_all_short(P.g))
+    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, true>), dim3(grid), dim3(64 * kSsWaves),
+                       (ssolve_lds<R, T, NP>()), s, P);
+  else
+    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, false>), dim3(grid), dim3(64 * kSsWaves),
+                       (ssolve_lds<R, T, NP>()), s, P);
   return hipGetLastError();
 }
 
@@ -584,10 +597,14 @@ static hipError_t ss_prepare_t() {
     if (e == hipSuccess)
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   };
-  set((const void*)k_ssolve<R, T, 16, false>, ssolve_lds<R, T, 16>());
-  set((const void*)k_ssolve<R, T, 16, true>, ssolve_lds<R, T, 16>());
-  set((const void*)k_ssolve<R, T, 32, false>, ssolve_lds<R, T, 32>());
-  set((const void*)k_ssolve<R, T, 32, true>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 16, false, false>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 16, true, false>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 32, false, false>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 32, true, false>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 16, false, true>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 16, true, true>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 32, false, true>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 32, true, true>, ssolve_lds<R, T, 32>());
   return e;
 }
 
