@@ -596,12 +596,14 @@ __device__ __forceinline__ int* flag_ptr(const FactorParams& P, int w, int r, in
 // chunks of all the products form one sequence, loaded one chunk ahead of
 // the MFMAs (two register buffers), so that only the first load's latency is
 // exposed; the chunk count per product is even, so the loop needs no tail.
+// G3: Gauss's three real MFMAs per complex product (the FP32 factor's early
+// updates; the last update of every tile and the diagonal worker's keep four).
 template <typename R, int T, int KQ>
 struct UpdChunk {
   cplx<R> a[KQ], b0[KQ], b1[KQ];
 };
 
-template <typename R, int T, int KQ>
+template <typename R, int T, int KQ, bool G3 = false>
 __device__ __forceinline__ void update_gemms(Acc2<R>& acc, const FactorParams& P, int w, int r,
                                              int t, int s0, int s1, int rb, int cp) {
   constexpr int NKC = T / 4 / KQ;  // chunks per product
@@ -622,11 +624,18 @@ __device__ __forceinline__ void update_gemms(Acc2<R>& acc, const FactorParams& P
       c.b1[q] = Bm[k * T + j0 + 16];
     }
   };
+  Gauss3<R> g;
+  if constexpr (G3) g.zero();
   auto mma = [&](const UpdChunk<R, T, KQ>& c) {
 #pragma unroll
     for (int q = 0; q < KQ; q++) {
-      cmfma<R, false, true>(acc.re[0], acc.im[0], c.a[q], c.b0[q]);
-      cmfma<R, false, true>(acc.re[1], acc.im[1], c.a[q], c.b1[q]);
+      if constexpr (G3) {
+        g.mma(c.a[q], c.b0[q], 0);
+        g.mma(c.a[q], c.b1[q], 1);
+      } else {
+        cmfma<R, false, true>(acc.re[0], acc.im[0], c.a[q], c.b0[q]);
+        cmfma<R, false, true>(acc.re[1], acc.im[1], c.a[q], c.b1[q]);
+      }
     }
   };
   UpdChunk<R, T, KQ> c0, c1;
@@ -638,6 +647,7 @@ __device__ __forceinline__ void update_gemms(Acc2<R>& acc, const FactorParams& P
     load(c0, min(idx + 2, N - 1));  // the last one reloads a chunk (unused)
     mma(c1);
   }
+  if constexpr (G3) g.template add_to<true>(acc);
 }
 
 // Tile flags.  Off-diagonal: 1 = partial (E done), 3 = final.  Diagonal:
@@ -906,7 +916,10 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_factor(FactorParams P) {
     }
     load_tile<R, T>(P, acc, w, r, t, partial, rb, cp);
     if (s_lo <= s_hi) wait_inputs(P, w, r, t, s_lo, s_hi, nullptr, FL_FINAL);
-    update_gemms<R, T, KU>(acc, P, w, r, t, s_lo, s_hi, rb, cp);
+    if (sizeof(R) == 4 && early)  // FP32 early updates: Gauss products
+      update_gemms<R, T, KU, true>(acc, P, w, r, t, s_lo, s_hi, rb, cp);
+    else
+      update_gemms<R, T, KU>(acc, P, w, r, t, s_lo, s_hi, rb, cp);
     acc_to_lds<R, T>(acc, lds, false, rb, cp);  // column-major in every case
     if (early) {
       __syncthreads();

@@ -28,8 +28,14 @@ def rhs(n, k, seed=0):
     return B, torch.as_tensor(B, device="cuda")
 
 
-def test_gmres_ir_converges_where_plain_refinement_stalls():
-    w = W.small("i", 32, 16, nu=1e-2)
+@pytest.mark.parametrize("nx,ny", [(32, 16), (24, 48)])
+def test_gmres_ir_converges_where_plain_refinement_stalls(nx, ny):
+    """At a shift 1e-7 |lambda| from an eigenvalue (kappa(M) u_32 >> 1) plain
+    refinement stalls and GMRES-IR with the FP32 factor as preconditioner
+    converges.  With T = 32 the 32 x 16 grid's band is one tile wide (every
+    update is a tile's last, four real MFMAs); the 24 x 48 grid's is three,
+    so its FP32 factor also has early updates, which take Gauss products."""
+    w = W.small("i", nx, ny, nu=1e-2)
     U, coef, L, phi, hx, hy = oracle_problem(w)
     lam = np.linalg.eigvals(L.toarray())
     lam0 = lam[np.argmax(lam.real)]
