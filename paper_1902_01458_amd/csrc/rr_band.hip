@@ -725,11 +725,14 @@ __device__ __forceinline__ void acc_to_lds(const Acc2<R>& acc, cplx<R>* lds, boo
   }
 }
 
-// Coherent copy of the T x T tile held column-major in LDS (leading dimension
-// LDT) to the stored tile X (column-major, or row-major when rowmajor):
-// consecutive threads write consecutive 8-byte words, so every store
-// instruction covers whole cache lines.
-template <typename R, int T>
+// Copy of the T x T tile held column-major in LDS (leading dimension LDT) to
+// the stored tile X (column-major, or row-major when rowmajor): consecutive
+// threads write consecutive 8-byte words, so every store instruction covers
+// whole cache lines.  CO: device-coherent stores (written through), for
+// tiles other workgroups of the launch read; the kernels after the
+// factorisation, whose tiles only the same workgroup or later launches
+// read, store plainly and keep them in the L2.
+template <typename R, int T, bool CO = true>
 __device__ __forceinline__ void lds_to_tile(const cplx<R>* S, cplx<R>* X, bool rowmajor) {
   typedef FGeom<T> G;
   constexpr int WPE = sizeof(cplx<R>) / 8;  // 8-byte words per element
@@ -739,7 +742,12 @@ __device__ __forceinline__ void lds_to_tile(const cplx<R>* S, cplx<R>* X, bool r
     const int wi = threadIdx.x + q * G::NT;
     const int idx = wi / WPE, o = idx / T, i = idx % T;
     const int e = rowmajor ? i * G::LDT + o : o * G::LDT + i;
-    if constexpr (WPE == 2) {
+    if constexpr (!CO) {
+      if constexpr (WPE == 2)
+        reinterpret_cast<double*>(X)[wi] = reinterpret_cast<const double*>(S)[2 * e + (wi & 1)];
+      else
+        X[idx] = S[e];
+    } else if constexpr (WPE == 2) {
       const double v = reinterpret_cast<const double*>(S)[2 * e + (wi & 1)];
       __hip_atomic_store(reinterpret_cast<double*>(X) + wi, v, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -761,13 +769,13 @@ __device__ __forceinline__ void tile_to_lds(const cplx<R>* X, cplx<R>* S) {
 }
 
 // acc -> stored tile X through the LDS staging area `stage` (T x LDT).
-template <typename R, int T>
+template <typename R, int T, bool CO = true>
 __device__ __forceinline__ void stage_store(const Acc2<R>& acc, cplx<R>* stage, cplx<R>* X,
                                             bool rowmajor, int rb, int cp) {
   __syncthreads();  // earlier readers of the staging area are done
   acc_to_lds<R, T>(acc, stage, false, rb, cp);
   __syncthreads();
-  lds_to_tile<R, T>(stage, X, rowmajor);
+  lds_to_tile<R, T, CO>(stage, X, rowmajor);
 }
 
 // Block-inverse LU of diagonal tile s (lu_blockinv), kept beside the chain tiles.
@@ -971,7 +979,7 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_diaginv(FactorParams P) {
   tile_to_lds<R, T>(lub_ptr<R, T>(P, w, m), lds);
   __syncthreads();
   inv_doubling<R, T, G::NW>(lds, G::LDT, aux);
-  lds_to_tile<R, T>(lds, tile_ptr<R, T>(P, w, m, m), false);
+  lds_to_tile<R, T, false>(lds, tile_ptr<R, T>(P, w, m, m), false);
 }
 
 // Tile `slot` of block row r's superblock-inverse area (BandGeom::sb_slot).
@@ -1095,7 +1103,8 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_sbinv(FactorParams P) {
       acc.zero();
       tile_gemm<R, T, KQ, true, G3>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false,
                                     MK_UNIT_LOWER, sacc, G::LDT, true, MK_NONE, rb, cp);
-      stage_store<R, T>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), false, rb, cp);
+      stage_store<R, T, false>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), false, rb,
+                               cp);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
@@ -1124,7 +1133,8 @@ __global__ __launch_bounds__(FGeom<T>::NT) void k_sbinv(FactorParams P) {
       acc.zero();
       tile_gemm<R, T, KQ, true, G3>(acc, tile_ptr<R, T>(P, w, s0 + i, s0 + i), T, false, MK_UPPER,
                                     sacc, G::LDT, true, MK_NONE, rb, cp);
-      stage_store<R, T>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), true, rb, cp);
+      stage_store<R, T, false>(acc, stage, sb_ptr<R, T>(P, w, s0 + i, sb_slot(i, j)), true, rb,
+                               cp);
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
