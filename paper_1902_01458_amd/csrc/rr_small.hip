@@ -64,14 +64,29 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, int k, const do
 #pragma unroll
     for (int c = 0; c < 2; c++) acc[a][c] = make_double2(0, 0);
   int64_t r0 = (int64_t)chunk * kChunkRows, r1 = min(n, r0 + kChunkRows);
+  // each stage's rows are loaded into registers during the previous stage's
+  // products, then staged in LDS
+  constexpr int NST = kSub * KM / 256;
+  double2 pf[NST];
+  auto fetch = [&](int64_t rb) {
+    const int64_t rows = min((int64_t)kSub, r1 - rb);
+#pragma unroll
+    for (int q = 0; q < NST; q++) {
+      const int idx = threadIdx.x + 256 * q, j = idx / kSub, rr = idx % kSub;
+      pf[q] = (rr < rows && j < k) ? Yw[(int64_t)j * n + rb + rr] : make_double2(0, 0);
+    }
+  };
+  fetch(r0);
   for (int64_t rb = r0; rb < r1; rb += kSub) {
     int rows = (int)min((int64_t)kSub, r1 - rb);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kSub * KM; idx += 256) {
-      int j = idx / kSub, rr = idx % kSub;
-      ys[rr][j] = (rr < rows && j < k) ? Yw[(int64_t)j * n + rb + rr] : make_double2(0, 0);
+#pragma unroll
+    for (int q = 0; q < NST; q++) {
+      const int idx = threadIdx.x + 256 * q;
+      ys[idx % kSub][idx / kSub] = pf[q];
     }
     __syncthreads();
+    fetch(rb + kSub);  // past the chunk: no rows, no loads
     if (Tm) {  // ys <- ys * T: thread (row rr, columns cg + 4 c)
       const int rr = t % kSub, cg = t / kSub;
       double2 o[KM / 4];
