@@ -100,14 +100,23 @@ __device__ __forceinline__ void sc_load_b(SChunk<R, T, NCB>& c, const cplx<R>* V
 // one add per operand element; the error of the imaginary part is bounded by
 // a small multiple of eps (|ar| + |ai|)(|br| + |bi|), like the four-product
 // form's up to a constant.  Flops are still counted as 8 per complex FMA.
+//
+// A last column block holding at most 8 of the caller's columns (k = 20: 16
+// plus 4) takes the real form instead, two MFMAs where Gauss takes three:
+//   [Re C | Im C] = [ar ai] [[br, bi], [-bi, br]],
+// lanes l%16 < 8 of the 16 output columns holding Re of column l%8 and the
+// others its Im (ss_mma, ss_load_b and the reduction's TR case).
 template <typename R, int NCB>
 struct SAcc {
   typename Mf<R>::v4 p1[NCB], p2[NCB], p3[NCB];
+  typename Mf<R>::v4 t;  // the last column block in real form (ss_mma's TR)
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int c = 0; c < NCB; c++)
 #pragma unroll
       for (int e = 0; e < 4; e++) { p1[c][e] = 0; p2[c][e] = 0; p3[c][e] = 0; }
+#pragma unroll
+    for (int e = 0; e < 4; e++) t[e] = 0;
   }
 };
 
@@ -333,17 +342,20 @@ __device__ __forceinline__ void ss_mask_a(cplx<R>* a, int mask, int rb, int q0) 
   }
 }
 
-template <typename R, int NP, int NCB, int N>
+template <typename R, int NP, int NCB, int N, bool TR>
 __device__ __forceinline__ void ss_load_b(cplx<R> (*b)[N], const cplx<R>* V, int q0) {
   const int l = threadIdx.x & 63;
 #pragma unroll
-  for (int cb = 0; cb < NCB; cb++)
+  for (int cb = 0; cb < NCB; cb++) {
+    const int col = 16 * cb + ((TR && cb == NCB - 1) ? (l & 7) : (l & 15));
 #pragma unroll
-    for (int q = 0; q < N; q++) b[cb][q] = V[(4 * (q0 + q) + (l >> 4)) * NP + 16 * cb + (l & 15)];
+    for (int q = 0; q < N; q++) b[cb][q] = V[(4 * (q0 + q) + (l >> 4)) * NP + col];
+  }
 }
 
-template <typename R, int NCB, int N, bool CA>
+template <typename R, int NCB, int N, bool CA, bool TR>
 __device__ __forceinline__ void ss_mma(SAcc<R, NCB>& acc, const cplx<R>* a, const cplx<R> (*b)[N]) {
+  const bool im_lane = (threadIdx.x & 8) != 0;  // lanes 8 .. 15 of each 16
 #pragma unroll
   for (int q = 0; q < N; q++) {
     const R ar = a[q].re, ai = CA ? -a[q].im : a[q].im;
@@ -351,9 +363,15 @@ __device__ __forceinline__ void ss_mma(SAcc<R, NCB>& acc, const cplx<R>* a, cons
 #pragma unroll
     for (int cb = 0; cb < NCB; cb++) {
       const R br = b[cb][q].re, bi = b[cb][q].im;
-      acc.p1[cb] = Mf<R>::op(ar, br, acc.p1[cb]);
-      acc.p2[cb] = Mf<R>::op(ai, bi, acc.p2[cb]);
-      acc.p3[cb] = Mf<R>::op(sa, br + bi, acc.p3[cb]);
+      if (TR && cb == NCB - 1) {
+        // [re | im] = [ar ai] [[br, bi], [-bi, br]]: two real MFMAs
+        acc.t = Mf<R>::op(ar, im_lane ? bi : br, acc.t);
+        acc.t = Mf<R>::op(ai, im_lane ? br : -bi, acc.t);
+      } else {
+        acc.p1[cb] = Mf<R>::op(ar, br, acc.p1[cb]);
+        acc.p2[cb] = Mf<R>::op(ai, bi, acc.p2[cb]);
+        acc.p3[cb] = Mf<R>::op(sa, br + bi, acc.p3[cb]);
+      }
     }
   }
 }
@@ -362,40 +380,40 @@ __device__ __forceinline__ void ss_mma(SAcc<R, NCB>& acc, const cplx<R>* a, cons
 // in pre) against the solved block V.  `later` issues the loads the products
 // do not need; it runs once the first operands' loads are issued, since
 // loads complete in order and the MFMAs would otherwise wait on them too.
-template <typename R, int T, int NP, bool CA, typename F>
+template <typename R, int T, int NP, bool CA, bool TR, typename F>
 __device__ __forceinline__ void ss_short(SAcc<R, NP / 16>& acc, SPre<R, T>& pre,
                                          const cplx<R>* X, const cplx<R>* V, int mask, int rb,
                                          bool xt, F&& later) {
   constexpr int NCB = NP / 16, PQ = ss_pq<R, T>(), NCK = (T / 4) / PQ;
   cplx<R> ba[NCB][PQ];
-  ss_load_b<R, NP, NCB, PQ>(ba, V, 0);
+  ss_load_b<R, NP, NCB, PQ, TR>(ba, V, 0);
   if constexpr (NCK == 1) {
     later();
     ss_mask_a<R, CA, PQ>(pre.a, mask, rb, 0);
-    ss_mma<R, NCB, PQ, CA>(acc, pre.a, ba);
+    ss_mma<R, NCB, PQ, CA, TR>(acc, pre.a, ba);
   } else {
     cplx<R> aa[PQ], ab[PQ], bb[NCB][PQ];
     ss_load_a<R, T, CA, PQ>(ab, X, rb, xt, PQ);
-    ss_load_b<R, NP, NCB, PQ>(bb, V, PQ);
+    ss_load_b<R, NP, NCB, PQ, TR>(bb, V, PQ);
     later();
     ss_mask_a<R, CA, PQ>(pre.a, mask, rb, 0);
-    ss_mma<R, NCB, PQ, CA>(acc, pre.a, ba);
+    ss_mma<R, NCB, PQ, CA, TR>(acc, pre.a, ba);
 #pragma unroll
     for (int c = 1; c < NCK; c++) {
       if (c % 2 == 1) {
         if (c + 1 < NCK) {
           ss_load_a<R, T, CA, PQ>(aa, X, rb, xt, (c + 1) * PQ);
-          ss_load_b<R, NP, NCB, PQ>(ba, V, (c + 1) * PQ);
+          ss_load_b<R, NP, NCB, PQ, TR>(ba, V, (c + 1) * PQ);
         }
         ss_mask_a<R, CA, PQ>(ab, mask, rb, c * PQ);
-        ss_mma<R, NCB, PQ, CA>(acc, ab, bb);
+        ss_mma<R, NCB, PQ, CA, TR>(acc, ab, bb);
       } else {
         if (c + 1 < NCK) {
           ss_load_a<R, T, CA, PQ>(ab, X, rb, xt, (c + 1) * PQ);
-          ss_load_b<R, NP, NCB, PQ>(bb, V, (c + 1) * PQ);
+          ss_load_b<R, NP, NCB, PQ, TR>(bb, V, (c + 1) * PQ);
         }
         ss_mask_a<R, CA, PQ>(aa, mask, rb, c * PQ);
-        ss_mma<R, NCB, PQ, CA>(acc, aa, ba);
+        ss_mma<R, NCB, PQ, CA, TR>(acc, aa, ba);
       }
     }
   }
@@ -421,8 +439,10 @@ __device__ __forceinline__ void ss_prefetch(SPre<R, T>& pre, const SSolveParams&
 
 // SHORT: every piece is short (the band and the superblock span at most
 // kSsWaves tiles), so the long-piece path is compiled out; its chunk buffers
-// would otherwise set the register count (in FP64 with spills).
-template <typename R, int T, int NP, bool ADJ, bool SHORT>
+// would otherwise set the register count (in FP64 with spills).  TR (short
+// pieces only): the last column block holds at most 8 of the caller's
+// columns and is formed in real form (SAcc).
+template <typename R, int T, int NP, bool ADJ, bool SHORT, bool TR>
 __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
   if (P.skip && __hip_atomic_load(P.skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   constexpr int NCB = NP / 16;
@@ -522,7 +542,7 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
             bool xt;
             const cplx<R>* X = ss_operand<R, T, ADJ>(P, pc, x, mask, xt);
             const cplx<R>* V = (pc.phase == 0 ? xw : cw) + (int64_t)x * T * NP;
-            ss_short<R, T, NP, ADJ>(acc, pre, X, V, mask, rb, xt, later);
+            ss_short<R, T, NP, ADJ, TR>(acc, pre, X, V, mask, rb, xt, later);
           } else {
             later();
           }
@@ -544,9 +564,17 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
 #pragma unroll
         for (int c = 0; c < NCB; c++)
 #pragma unroll
-          for (int e = 0; e < 4; e++)
-            red[(wave * 16 + Mf<R>::row(l, e)) * NP + 16 * c + (l & 15)] =
-                sc_finish<R, NCB>(acc, c, e, pc.phase == 0);
+          for (int e = 0; e < 4; e++) {
+            const int rw = (wave * 16 + Mf<R>::row(l, e)) * NP;
+            if (TR && c == NCB - 1) {  // lane l%16 < 8: re of column l%8, else its im
+              R* rr = reinterpret_cast<R*>(red);
+              const int half = (l >> 3) & 1, col = 16 * c + (l & 7);
+              rr[2 * (rw + col) + half] = pc.phase == 0 ? -acc.t[e] : acc.t[e];
+              rr[2 * (rw + col + 8) + half] = (R)0;  // columns 8 .. 15 of the block
+            } else {
+              red[rw + 16 * c + (l & 15)] = sc_finish<R, NCB>(acc, c, e, pc.phase == 0);
+            }
+          }
         __syncthreads();
         if (want_ys) rhs = make_double2((double)ys.re, (double)ys.im);
         if (mine) {
@@ -581,11 +609,14 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
 
 template <typename R, int T, int NP, bool ADJ>
 static hipError_t ss_launch(const SSolveParams& P, int grid, hipStream_t s) {
-  if (ss_all_short(P.g))
-    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, true>), dim3(grid), dim3(64 * kSsWaves),
+  if (ss_all_short(P.g) && P.k - (NP - 16) <= 8)  // the last block's columns: at most 8
+    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, true, true>), dim3(grid), dim3(64 * kSsWaves),
+                       (ssolve_lds<R, T, NP>()), s, P);
+  else if (ss_all_short(P.g))
+    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, true, false>), dim3(grid), dim3(64 * kSsWaves),
                        (ssolve_lds<R, T, NP>()), s, P);
   else
-    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, false>), dim3(grid), dim3(64 * kSsWaves),
+    hipLaunchKernelGGL((k_ssolve<R, T, NP, ADJ, false, false>), dim3(grid), dim3(64 * kSsWaves),
                        (ssolve_lds<R, T, NP>()), s, P);
   return hipGetLastError();
 }
@@ -597,14 +628,18 @@ static hipError_t ss_prepare_t() {
     if (e == hipSuccess)
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   };
-  set((const void*)k_ssolve<R, T, 16, false, false>, ssolve_lds<R, T, 16>());
-  set((const void*)k_ssolve<R, T, 16, true, false>, ssolve_lds<R, T, 16>());
-  set((const void*)k_ssolve<R, T, 32, false, false>, ssolve_lds<R, T, 32>());
-  set((const void*)k_ssolve<R, T, 32, true, false>, ssolve_lds<R, T, 32>());
-  set((const void*)k_ssolve<R, T, 16, false, true>, ssolve_lds<R, T, 16>());
-  set((const void*)k_ssolve<R, T, 16, true, true>, ssolve_lds<R, T, 16>());
-  set((const void*)k_ssolve<R, T, 32, false, true>, ssolve_lds<R, T, 32>());
-  set((const void*)k_ssolve<R, T, 32, true, true>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 16, false, false, false>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 16, true, false, false>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 32, false, false, false>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 32, true, false, false>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 16, false, true, false>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 16, true, true, false>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 32, false, true, false>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 32, true, true, false>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 16, false, true, true>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 16, true, true, true>, ssolve_lds<R, T, 16>());
+  set((const void*)k_ssolve<R, T, 32, false, true, true>, ssolve_lds<R, T, 32>());
+  set((const void*)k_ssolve<R, T, 32, true, true, true>, ssolve_lds<R, T, 32>());
   return e;
 }
 
