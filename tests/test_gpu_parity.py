@@ -308,3 +308,32 @@ def test_first_refined_solve_measures_contraction(k, probed):
     first = 1 if probed else 2
     assert counts == [first, 1, 1] * 2, counts
     f.free()
+
+
+def test_adjoint_first_refined_solve_measures_with_a_second_correction():
+    """Probe columns ride only in forward solves: a first refined solve that
+    is an adjoint one measures the contraction by a second correction, and
+    the solves after it stop after one; both meet the tolerance against
+    LAPACK's banded solve."""
+    w = W.small("pa", 40, 24, nu=2e-2)
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    prob = rr().BurgersProblem.from_workload(w)
+    oms = [0.4, 2.5, 1.1]
+    k = 20
+    f = rr().factor(prob, oms, "mixed", k_max=k, tile=32, refine_tol=1e-8)
+    rng = np.random.Generator(np.random.PCG64(37))
+    Bm = rng.standard_normal((3, k, w.n)) + 1j * rng.standard_normal((3, k, w.n))
+    Bt = torch.tensor(Bm, device="cuda")
+    Z = to_np(f.adjoint_solve(Bt))
+    f.check()
+    first = f.refine_count()
+    X = to_np(f.solve(Bt))
+    f.check()
+    second = f.refine_count()
+    for i, om in enumerate(oms):
+        S = ShiftedSolver(op.shifted(L, om), "gb")
+        ref, refh = S.solve(Bm[i].T).T, S.solve_adjoint(Bm[i].T).T
+        assert np.linalg.norm(X[i] - ref) / np.linalg.norm(ref) <= 1e-8
+        assert np.linalg.norm(Z[i] - refh) / np.linalg.norm(refh) <= 1e-8
+    assert (first, second) == (2, 1), (first, second)
+    f.free()
