@@ -352,10 +352,13 @@ def main():
         bw = byt / (res["solve_ms"] * 1e-3) / 1e9
         np_ = 16 * ((w.k + 15) // 16)
         T = res["tune"]["tile"]
-        # the superblock solve's short-piece form when the half-band spans at most 8 tiles
-        short = "true" if (b + T - 1) // T <= 8 else "false"
+        # the superblock solve's short-piece form when the half-band spans at most 8
+        # tiles, with its last column block in real form when that holds at most 8
+        # of the k columns
+        short = (b + T - 1) // T <= 8
+        tail = short and w.k - (np_ - 16) <= 8
         kname = (f"k_solve2<{name},{T},16,false>" if (res["tune"].get("superblock") or 0) < 0
-                 else f"k_ssolve<{name},{T},{np_},false,{short}>")
+                 else f"k_ssolve<{name},{T},{np_},false,{str(short).lower()},{str(tail).lower()}>")
         return {"bound": "hbm", "achieved": bw, "peak": 8000.0, "unit": "GB/s",
                 "frac": bw / 8000.0, "bytes_per_launch": byt, "traffic": traffic(kname),
                 "kernel": f"{kname} (forward solve of the eq. 9 recovery, all {n_om} shifts x "
