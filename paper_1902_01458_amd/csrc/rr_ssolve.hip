@@ -162,6 +162,7 @@ struct SSolveParams {
   uint32_t* status;
   int teams;         // min(kTeams, n_omega)
   const uint32_t* skip;  // optional: non-zero at run time = nothing to do
+  int ahead;         // hold a second ticket in the home team (see k_ssolve)
 };
 
 constexpr int kTeams = 8;  // XCDs of gfx950
@@ -469,7 +470,11 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
     // are smaller tickets, all finished.  Serving another team (after its
     // own ran out) it takes one ticket at a time, as a piece of that team
     // then never waits on a ticket held back behind a piece of another team.
-    const bool ahead = tt == 0;
+    // Where a team's workgroups outnumber the pieces of a phase of all its
+    // shifts (P.ahead = 0: one round), every workgroup takes one ticket at a
+    // time: a second ticket would bind a piece of the next phase to a
+    // workgroup still busy with another shift's piece, while others are free.
+    const bool ahead = tt == 0 && P.ahead;
     int64_t cur = wg_ticket(tick, &s_ticket);
     SPiece pc = ss_decode(cur, team, P.teams, nw, npc, RPT, P.g);
     SPre<R, T> pre;
@@ -675,6 +680,18 @@ hipError_t launch_ssolve(const BandGeom& g, int n, int n_omega, int k, bool fp32
   SSolveParams P{g, n, n_omega, k, tiles, (const double2*)Bm, bstride, (double2*)X, xs, cbuf,
                  cnt, (uint32_t*)(cnt + npiece), status, n_omega < kTeams ? n_omega : kTeams,
                  skip};
+  {  // a second ticket only where a phase takes more than one round of a team
+    static int cus = 0;
+    if (cus == 0) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          cus <= 0)
+        cus = 256;
+    }
+    const int per_team = (n_omega + P.teams - 1) / P.teams;
+    P.ahead = (int64_t)npc * per_team > cus / kTeams ? 1 : 0;
+  }
   hipError_t e = launch_fill_u32((uint32_t*)cnt, 0u, ssolve_counters(g, n_omega), s);
   if (e != hipSuccess) return e;
   const int64_t total = npiece * npc;
