@@ -690,7 +690,7 @@ hipError_t launch_ssolve(const BandGeom& g, int n, int n_omega, int k, bool fp32
         cus = 256;
     }
     const int per_team = (n_omega + P.teams - 1) / P.teams;
-    P.ahead = (int64_t)npc * per_team > cus / kTeams ? 1 : 0;
+    P.ahead = (int64_t)npc * per_team > cus / P.teams ? 1 : 0;  // a team's CUs
   }
   hipError_t e = launch_fill_u32((uint32_t*)cnt, 0u, ssolve_counters(g, n_omega), s);
   if (e != hipSuccess) return e;
