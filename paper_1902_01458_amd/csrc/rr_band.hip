@@ -697,13 +697,16 @@ __device__ __forceinline__ void wait_inputs(const FactorParams& P, int w, int r,
   __syncthreads();
 }
 
-// Every thread's stores are complete, then thread 0 releases (L2 write-back)
-// and sets the flag; barriers close the interval on both sides.
+// Every thread's stores are complete, then thread 0 releases and sets the
+// flag; barriers close the interval on both sides.  Everything a task hands
+// over is stored device-coherent (written through), so the stores' completion
+// is the whole release: no L2 write-back precedes the flag, and the release
+// fence is at workgroup scope.
 __device__ __forceinline__ void publish(int* flag, int value) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();

@@ -45,7 +45,10 @@ __device__ __forceinline__ void latch(uint32_t* status, uint32_t bit) {
 // agent-scope atomic store is device-coherent (sc1, written through), and the
 // s_waitcnt before the release covers its completion; with every handed-over
 // tile stored this way none of 48 factorisations was wrong.  Readers keep
-// ordinary loads after their acquire.
+// ordinary loads after their acquire.  As every handed-over value is written
+// through, a writer's release needs no L2 write-back: the factorisation and
+// the solves wait for their stores' completion and release at workgroup
+// scope before the flag or count.
 __device__ __forceinline__ void st_coherent(cplx<float>* p, cplx<float> v) {
   uint64_t bits = (uint64_t)__float_as_uint(v.re) | ((uint64_t)__float_as_uint(v.im) << 32);
   __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bits, __ATOMIC_RELAXED,
