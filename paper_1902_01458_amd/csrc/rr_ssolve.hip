@@ -470,9 +470,9 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
     // are smaller tickets, all finished.  Serving another team (after its
     // own ran out) it takes one ticket at a time, as a piece of that team
     // then never waits on a ticket held back behind a piece of another team.
-    // Where a team's workgroups outnumber the pieces of a phase of all its
-    // shifts (P.ahead = 0: one round), every workgroup takes one ticket at a
-    // time: a second ticket would bind a piece of the next phase to a
+    // Where the pieces of a phase of all a team's shifts fit one round of
+    // the team's workgroups (P.ahead = 0), every workgroup takes one ticket
+    // at a time: a second ticket would bind a piece of the next phase to a
     // workgroup still busy with another shift's piece, while others are free.
     const bool ahead = tt == 0 && P.ahead;
     int64_t cur = wg_ticket(tick, &s_ticket);
