@@ -470,8 +470,8 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
     // are smaller tickets, all finished.  Serving another team (after its
     // own ran out) it takes one ticket at a time, as a piece of that team
     // then never waits on a ticket held back behind a piece of another team.
-    // In FP64, where the pieces of a phase of all a team's shifts fit one
-    // round of the team's workgroups (P.ahead = 0, launch_ssolve), every
+    // Where the pieces of a phase of all a team's shifts fit one round of
+    // the team's workgroups (P.ahead = 0; launch_ssolve sets it), every
     // workgroup takes one ticket at a time: a second ticket would bind a
     // piece of the next phase to a workgroup still busy with another shift's
     // piece, while others are free.
@@ -681,12 +681,13 @@ hipError_t launch_ssolve(const BandGeom& g, int n, int n_omega, int k, bool fp32
   SSolveParams P{g, n, n_omega, k, tiles, (const double2*)Bm, bstride, (double2*)X, xs, cbuf,
                  cnt, (uint32_t*)(cnt + npiece), status, n_omega < kTeams ? n_omega : kTeams,
                  skip};
-  {  // a second ticket where a phase takes more than one round of a team, and
-     // always in FP32: there the next piece's whole factor tile is prefetched
-     // while the current one runs, and taking its ticket only at the end
-     // leaves that load no time (FP32, 16 shifts, 4 block rows: forward /
-     // adjoint 32.1 / 33.4 ms with the second ticket, 34.0 / 42.0 without;
-     // FP64, which prefetches a quarter tile: 42.4 with, 38.9 without)
+  {  // a second ticket where a phase's pieces outnumber a team's CUs, and in
+     // FP32 also where they just fill them: without slack the second ticket
+     // is the only lead for FP32's whole-tile prefetch of the next piece
+     // (FP32, 16 shifts, 4 block rows: forward / adjoint 32.1 / 33.4 ms with
+     // it, 34.0 / 42.0 without; FP64, which prefetches a quarter tile: 42.4
+     // with, 38.9 without).  With slack (one shift: 32 pieces for 256 CUs)
+     // one ticket each already reaches phases ahead.
     static int cus = 0;
     if (cus == 0) {
       int dev = 0;
@@ -696,7 +697,8 @@ hipError_t launch_ssolve(const BandGeom& g, int n, int n_omega, int k, bool fp32
         cus = 256;
     }
     const int per_team = (n_omega + P.teams - 1) / P.teams;
-    P.ahead = fp32 || (int64_t)npc * per_team > cus / P.teams ? 1 : 0;  // a team's CUs
+    const int64_t pieces = (int64_t)npc * per_team, team_cus = cus / P.teams;
+    P.ahead = (fp32 ? pieces >= team_cus : pieces > team_cus) ? 1 : 0;
   }
   hipError_t e = launch_fill_u32((uint32_t*)cnt, 0u, ssolve_counters(g, n_omega), s);
   if (e != hipSuccess) return e;
