@@ -128,7 +128,7 @@ EPS32 = 2.0 ** -24   # unit roundoff, FP32
 
 def conditioning_report(L: sp.spmatrix, omega: complex, Omega: np.ndarray, q: int = 0,
                         unpivoted: bool = True, norm_iters: int = 200) -> dict:
-    """What bounds parity at one shift (the survey's O14 and R12 readings).
+    """What bounds parity at one shift: conditioning, gaps and the accuracy floor.
 
     From one run of Algorithm 1 (resolvent.randomized_resolvent, pivoted LU)
     with test matrix Omega and q subspace iterations:
@@ -176,7 +176,7 @@ def conditioning_report(L: sp.spmatrix, omega: complex, Omega: np.ndarray, q: in
 
 
 def parity_tolerance(tol: float, report: dict) -> float:
-    """Reading R12: the tolerance a parity test may use at this shift.  When
+    """The tolerance a parity test may use at this shift.  When
     the predicted floor exceeds tol / 10 it is max(tol, 10 x the measured
     floor between the pivoted and the unpivoted LU), otherwise tol."""
     if report["floor_pred"] <= tol / 10 or "floor_measured" not in report:

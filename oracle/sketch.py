@@ -14,8 +14,8 @@ counter (r, j, stream, 0) under key (seed low word, seed high word):
 where m1, m2 are the top 53 bits of the 64-bit words (x0:x1) and (x2:x3).
 Column j does not depend on k, so sketches of growing width are nested.
 
-Other test matrices named in Section 2.2.2 (readings of this build; the paper
-gives no formulas):
+Other test matrices named in Section 2.2.2 (our readings; the paper gives no
+formulas):
   * Rademacher: real +-1 entries, the sign being the top bit of x0 at the
     same counter (r, j, stream, 0); nested in k like the Gaussian one.
   * ultrasparse Rademacher (sparse sign): each row has zeta nonzeros, +-1 as
