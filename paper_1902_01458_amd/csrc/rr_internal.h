@@ -48,7 +48,8 @@ __device__ __forceinline__ void latch(uint32_t* status, uint32_t bit) {
 // ordinary loads after their acquire.  As every handed-over value is written
 // through, a writer's release needs no L2 write-back: the factorisation and
 // the solves wait for their stores' completion and release at workgroup
-// scope before the flag or count.
+// scope before the flag or count.  (The superblock solve stores plainly where
+// its writer and readers share one XCD, and so its L2: a team per XCD.)
 __device__ __forceinline__ void st_coherent(cplx<float>* p, cplx<float> v) {
   uint64_t bits = (uint64_t)__float_as_uint(v.re) | ((uint64_t)__float_as_uint(v.im) << 32);
   __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bits, __ATOMIC_RELAXED,

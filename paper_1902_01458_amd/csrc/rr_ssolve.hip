@@ -31,9 +31,10 @@
 // loads that piece's factor tile during the current products, so that a step
 // finds the operands of its pieces in registers.  Data handed between
 // workgroups (c and the sweep's blocks) is stored device-coherent
-// (st_coherent, written through); the counter is incremented once those
-// stores have completed, and readers poll it (four polls in flight), then
-// acquire.
+// (st_coherent, written through), or, when every team is one XCD serving
+// only itself (eight shifts or more), with plain stores into that XCD's L2;
+// the counter is incremented once those stores have completed, and readers
+// poll it (four polls in flight), then acquire.
 #include "rr_mfma.h"
 
 namespace rr {
@@ -163,6 +164,7 @@ struct SSolveParams {
   int teams;         // min(kTeams, n_omega)
   const uint32_t* skip;  // optional: non-zero at run time = nothing to do
   int ahead;         // hold a second ticket in the home team (see k_ssolve)
+  int local;         // every team is one XCD and serves only itself (see k_ssolve)
 };
 
 constexpr int kTeams = 8;  // XCDs of gfx950
@@ -213,7 +215,8 @@ __device__ __forceinline__ int64_t ss_wait(int* c, int want, uint32_t* status, u
 
 // Every thread's stores are complete, then thread 0 counts the piece done.
 // Everything a piece hands over is stored device-coherent (st_coherent,
-// written through), so waiting for the stores is the whole release: no L2
+// written through) or, in a team confined to one XCD, into the L2 its
+// readers share, so waiting for the stores is the whole release: no L2
 // write-back is needed before the count.  Barriers close the interval on
 // both sides.
 __device__ __forceinline__ void ss_done(int* c) {
@@ -458,7 +461,13 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
   const int NB = P.g.NB, NS = P.g.NS();
   const int npc = P.g.P * RPT;  // pieces per superblock phase
   const int home = xcc_id() % P.teams;
-  for (int tt = 0; tt < P.teams; tt++) {
+  // With P.local (a team per XCD, launch_ssolve) a workgroup serves its own
+  // team only: every piece of a shift then runs on one XCD, whose L2 holds
+  // what one piece hands to the next, so the hand-over is stored plainly
+  // (the count that announces it is still a device-coherent atomic, and the
+  // reader's acquire drops its stale L1 lines).
+  const int nserve = P.local ? 1 : P.teams;
+  for (int tt = 0; tt < nserve; tt++) {
     const int team = (home + tt) % P.teams;
     const int nw = (P.n_omega - team + P.teams - 1) / P.teams;  // this team's shifts
     const int64_t total = (int64_t)2 * NS * 2 * nw * npc;
@@ -592,7 +601,10 @@ __global__ __launch_bounds__(64 * kSsWaves) void k_ssolve(SSolveParams P) {
             sm += p.im;
           }
           cplx<R>* dst = pc.phase == 0 ? cw + (int64_t)pc.i * T * NP : xw + (int64_t)s * T * NP;
-          st_coherent(dst + (16 * rb + er) * NP + ec, cplx<R>{sr, sm});
+          if (P.local)
+            dst[(16 * rb + er) * NP + ec] = cplx<R>{sr, sm};
+          else
+            st_coherent(dst + (16 * rb + er) * NP + ec, cplx<R>{sr, sm});
           if (pc.phase == 1 && pc.second) {  // the solution into the caller's block
             const int64_t r = (int64_t)s * T + 16 * rb + er;
             if (ec < P.k && r < P.n)
@@ -704,6 +716,9 @@ hipError_t launch_ssolve(const BandGeom& g, int n, int n_omega, int k, bool fp32
   if (e != hipSuccess) return e;
   const int64_t total = npiece * npc;
   if (grid > total) grid = (int)total;
+  // a team per XCD, each with workgroups of its own (the launch deals them
+  // to the XCDs in turn): handoffs within one L2
+  P.local = P.teams == kTeams && grid >= 8 * kTeams ? 1 : 0;
   if (fp32) {
     if (g.T == 64) return ss_dispatch<float, 64>(P, NP, adjoint, grid, s);
     if (g.T == 32) return ss_dispatch<float, 32>(P, NP, adjoint, grid, s);

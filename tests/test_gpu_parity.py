@@ -264,6 +264,36 @@ def test_superblock_solve_matches_oracle(prec, nx, ny, tile, k, sb):
     f.free()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("tile,sb", [(32, 3), (64, 4)])
+def test_superblock_solve_with_a_team_per_xcd_matches_oracle(prec, tile, sb):
+    """Nine shifts: the solve's workgroups form a team per XCD, each serving
+    only its own shifts (one team holds two) and handing blocks over through
+    its XCD's L2 with plain stores.  Forward and adjoint solves against
+    LAPACK's banded solve, at the tolerances of the test above."""
+    w = W.small("sb9", 16, 96, nu=2e-2)
+    U, coef, L, phi, hx, hy = oracle_problem(w)
+    prob = rr().BurgersProblem.from_workload(w)
+    oms = [0.25 * 1.45 ** i for i in range(9)]
+    k = 20
+    f = rr().factor(prob, oms, prec, k_max=k, tile=tile, superblock=sb, refine_tol=1.0)
+    rng = np.random.Generator(np.random.PCG64(19))
+    Bm = rng.standard_normal((len(oms), k, w.n)) + 1j * rng.standard_normal((len(oms), k, w.n))
+    Bt = torch.tensor(Bm, device="cuda")
+    X = to_np(f.solve(Bt))
+    Z = to_np(f.adjoint_solve(Bt))
+    f.check()
+    tol = 1e-11 if prec == "fp64" else 1e-4
+    for i, om in enumerate(oms):
+        S = ShiftedSolver(op.shifted(L, om), "gb")
+        ref = S.solve(Bm[i].T).T
+        refh = S.solve_adjoint(Bm[i].T).T
+        ex = np.linalg.norm(X[i] - ref) / np.linalg.norm(ref)
+        ez = np.linalg.norm(Z[i] - refh) / np.linalg.norm(refh)
+        assert ex <= tol and ez <= tol, (i, ex, ez)
+    f.free()
+
+
 @pytest.mark.parametrize("k,probed", [(10, True), (20, True), (16, False)])
 def test_first_refined_solve_measures_contraction(k, probed):
     """The first refined mixed solve after a factorisation measures the
